@@ -1,0 +1,181 @@
+/*
+ * epi.h -- C ABI of the MI355X (gfx950) solver library for reversed-gradient EPI
+ * susceptibility-artifact correction on the face-staggered grid.
+ *
+ * Method: Macdonald & Ruthotto, "Efficient Numerical Optimization for Susceptibility
+ * Artifact Correction of EPI-MRI". Section 3 defines the discretised problem, Section 4.1
+ * the Gauss-Newton-PCG solver with the block-Jacobi preconditioner, Section 4.2 the ADMM
+ * splitting (line-separable b-step solved by SQP with an active-set QP, DCT-diagonalised
+ * z-step).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout. All device arrays are float32 in the canonical layout: the phase-encoding (PE)
+ *   axis is contiguous. With cell counts m = (M, m2, m3) (m[0] = PE axis; m3 = 1 in 2D):
+ *     cell  (c, j, k), c in [0, M):      index c + M * (j + m2 * k)       (N = M m2 m3)
+ *     face  (i, j, k), i in [0, M]:      index i + (M + 1) * (j + m2 * k) (n = (M+1) m2 m3)
+ *   Face i of PE line (j, k) sits at PE coordinate i * h[0]; cell c at (c + 1/2) * h[0].
+ *   The field b is in physical length units (the same units as h).
+ * Ownership. Pointers named d_* are device pointers owned by the caller. epi_setup keeps
+ *   borrowed pointers to the two images; they must stay valid and unchanged until
+ *   epi_destroy. The problem handle owns its own device workspace.
+ * Streams. Every kernel of a handle runs on the hipStream_t given to epi_setup (NULL =
+ *   the default stream). Calls that return host scalars synchronise that stream before
+ *   returning. One handle must not be used by two host threads at the same time.
+ * Errors. No exception crosses the ABI. A non-OK status leaves a message readable with
+ *   epi_last_error() (thread-local, valid until the next failing call of that thread).
+ *   EPI_EINVAL: bad argument (null pointer, ndim not 2/3, m[a] < 1 or M < 2, h <= 0,
+ *   alpha < 0, rho <= 0, a size beyond the limits below). EPI_EINFEASIBLE: the starting
+ *   field violates the constraint (|D1 b| < 1 for GN-PCG, |D1 b| <= 1 for ADMM).
+ *   EPI_ENUMERIC: NaN/Inf met in the inputs or the iteration. EPI_EHIP: a HIP runtime
+ *   error (message carries the HIP error string). EPI_ENOMEM: device allocation failed.
+ *   Hitting an iteration cap is EPI_OK with converged = 0.
+ * Limits. M + 1 <= 512 faces per PE line; m2 <= 256 and m3 <= 256 (the DCT axes).
+ */
+#ifndef EPI_H_
+#define EPI_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EPI_ABI_VERSION 1
+
+typedef enum {
+  EPI_OK = 0,
+  EPI_EINVAL = 1,
+  EPI_ENOMEM = 2,
+  EPI_EINFEASIBLE = 3,
+  EPI_ENUMERIC = 4,
+  EPI_EHIP = 5,
+  EPI_ENOTSUP = 6
+} epi_status;
+
+/* Arithmetic of the z-step DCT products. FP32: float32 matrix-core products (the plain
+ * single-precision solver). MIXED: three-term split-bfloat16 products (hi*hi + hi*lo +
+ * lo*hi, float32 accumulation). Everything else is float32 with float64 reductions in
+ * both modes. */
+typedef enum { EPI_PREC_FP32 = 0, EPI_PREC_MIXED = 1 } epi_precision;
+
+/* Preconditioner of the GN-PCG inner solve (Section 4.1): block-Jacobi (eq. Pblock; one
+ * SPD tridiagonal system per PE line), Jacobi (diagonal of H_JGN), or none. */
+typedef enum { EPI_PRECOND_BLOCK = 0, EPI_PRECOND_JACOBI = 1, EPI_PRECOND_NONE = 2 } epi_precond;
+
+/* Problem geometry and weights (Section 3). h = voxel edges (h[2] = 1 in 2D); the cell
+ * volume v = h[0] h[1] h[2] plays the role of the paper's h^3. alpha weights the
+ * smoothness regulariser S, beta the penalty P (default 10), gamma the identity shift of
+ * the approximate Hessians (default 1e-3, unscaled). */
+typedef struct {
+  int32_t ndim;
+  int32_t m[3];
+  double h[3];
+  double alpha;
+  double beta;
+  double gamma;
+  int32_t precision; /* epi_precision */
+} epi_grid;
+
+/* Objective terms at a field b: J = D + alpha S (+ P when the penalty is requested).
+ * D = (v/2)|r(b)|^2 (eq. D), S = (v/2)(|D1 b|^2 + |D2 b|^2 + |D3 b|^2) (eq. S),
+ * P = beta v sum phi(D1 b) (eq. P). feasible = 1 iff every |D1 b| < 1 (P finite). */
+typedef struct {
+  double J, D, S, P;
+  int32_t feasible;
+} epi_terms;
+
+/* GN-PCG options (Section 4.1). Defaults from epi_gn_default_opts: max_iter 10,
+ * pcg_max 30, precond BLOCK, ls_max 10, use_stopping 1, eta 0.1 (eq. inexactGNsolve),
+ * eps_obj 1e-3, eps_iter 1e-2, eps_grad 1e-2 (eq. stopping1), ls_c1 1e-4 (Armijo),
+ * rel_grad_tol 0 (off; > 0 also stops when |grad| <= rel_grad_tol |grad at b0|). */
+typedef struct {
+  int32_t max_iter, pcg_max, precond, ls_max, use_stopping;
+  double eta, eps_obj, eps_iter, eps_grad, ls_c1, rel_grad_tol;
+} epi_gn_opts;
+
+/* GN-PCG report. The arrays are host arrays owned by the caller, each of length
+ * max_iter + 1 (J, grad_norm: entry 0 is the starting point) or max_iter (the others);
+ * any of them may be NULL. iters = GN steps taken; ls_failed = 1 if the last step found
+ * no sufficient decrease in ls_max trials (the iteration stops there, b unchanged). */
+typedef struct {
+  int32_t iters, converged, status, ls_failed;
+  double *J, *grad_norm, *pcg_relres, *step;
+  int32_t *pcg_iters;
+} epi_gn_report;
+
+/* ADMM options (Section 4.2). Defaults from epi_admm_default_opts: max_iter 100,
+ * sqp_iters 1 (linearisations per b-step), check_every 8 (iterations between host polls
+ * of the device-side stopping flag; results do not depend on it), rho 1e3,
+ * eps_abs = eps_rel = 0.2 (eq. admmStop). */
+typedef struct {
+  int32_t max_iter, sqp_iters, check_every;
+  double rho, eps_abs, eps_rel;
+} epi_admm_opts;
+
+/* ADMM report. Host arrays of length max_iter owned by the caller (NULL allowed):
+ * per-iteration primal residual |b - z|, dual residual rho v |z_k - z_k+1| and their
+ * tolerances (eq. admmStop, newest iterates). max_active = largest number of active
+ * constraints of one PE line at exit of any b-step; hard_lines = total count of
+ * (iteration, line) pairs that needed more than the unconstrained step. */
+typedef struct {
+  int32_t iters, converged, status, max_active;
+  int64_t hard_lines;
+  double *r_pri, *r_dual, *eps_pri, *eps_dual;
+} epi_admm_report;
+
+typedef struct epi_problem epi_problem;
+
+/* Library ABI version (EPI_ABI_VERSION). */
+int32_t epi_abi_version(void);
+
+/* Fill option structs with the paper's defaults (see above). */
+void epi_gn_default_opts(epi_gn_opts* opts);
+void epi_admm_default_opts(epi_admm_opts* opts);
+
+/* Create a problem handle for the image pair I_v (d_Iplus) and I_-v (d_Iminus), each N
+ * floats in canonical cell layout (Section 3, the discrete distance eq. D). stream is a
+ * hipStream_t (or NULL). Allocates the device workspace and the DCT tables; checks the
+ * images for NaN/Inf (EPI_ENUMERIC). On success *out owns the workspace; release it with
+ * epi_destroy. */
+epi_status epi_setup(const epi_grid* grid, const float* d_Iplus, const float* d_Iminus,
+                     void* stream, epi_problem** out);
+
+/* Evaluate the objective terms at d_b (n floats): D, S and, if with_penalty != 0, P
+ * (eq. D, eq. S, eq. P). If d_grad is not NULL it receives grad J (with_penalty = 0) or
+ * grad J_GN (with_penalty != 0), n floats (eq. dJ, eq. dJGN). Synchronises the stream. */
+epi_status epi_objective(epi_problem* p, const float* d_b, int32_t with_penalty,
+                         epi_terms* out, float* d_grad);
+
+/* The non-separable smoothness solve of the ADMM z-step (Section 4.2, eq. dctdiag):
+ * d_z = (alpha v (D2'D2 + D3'D3) + rho v I)^{-1} rho v d_w, by the orthonormal 2D DCT over
+ * the two non-PE axes in the arithmetic of grid->precision. d_w and d_z are n floats and
+ * may alias. Does not synchronise. */
+epi_status epi_smooth_solve(epi_problem* p, const float* d_w, double rho, float* d_z);
+
+/* Inexact Gauss-Newton-PCG on J_GN = D + alpha S + P (Section 4.1, eq. GNstep,
+ * eq. inexactGNstep): d_b holds the starting guess on entry (must satisfy |D1 b| < 1) and
+ * the result on exit. The PCG inner solve, Armijo line search and stopping tests run on
+ * the device; the host reads one report row per GN step. */
+epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts* opts,
+                           epi_gn_report* rep);
+
+/* Scaled ADMM (Section 4.2, eq. admmStep1-3): d_b, d_z, d_u (n floats each) hold the
+ * state (b^k, z^k, u^k) on entry and on exit, so a solve can be resumed by calling again.
+ * The starting b must satisfy |D1 b| <= 1. Every iteration runs as a fixed kernel
+ * sequence with a device-side stopping flag (eq. admmStop, float64 norms); kernels after
+ * convergence are no-ops, so the state on exit is the state at the stopping iteration. */
+epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
+                          const epi_admm_opts* opts, epi_admm_report* rep);
+
+/* Release the handle and its workspace (NULL is a no-op). */
+void epi_destroy(epi_problem* p);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char* epi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPI_H_ */

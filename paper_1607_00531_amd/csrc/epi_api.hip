@@ -1,0 +1,788 @@
+// Host runtime of the EPI solver library: problem handle, workspace, DCT tables, solver
+// drivers and the C ABI declared in include/epi.h.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "epi.h"
+#include "epi_common.hpp"
+#include "epi_launch.hpp"
+
+using namespace epi;
+
+#define EPI_API extern "C" __attribute__((visibility("default")))
+
+// ------------------------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static epi_status fail(epi_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(e_ == hipErrorOutOfMemory ? EPI_ENOMEM : EPI_EHIP, "%s: %s (%s:%d)", \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                  \
+  } while (0)
+
+#define CHKLAUNCH()                                                                   \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess)                                                             \
+      return fail(EPI_EHIP, "kernel launch: %s (%s:%d)", hipGetErrorString(e_),        \
+                  __FILE__, __LINE__);                                                \
+  } while (0)
+
+// ------------------------------------------------------------------------------------
+// the handle
+// ------------------------------------------------------------------------------------
+struct epi_problem {
+  epi_grid grid;
+  int M, m2, m3, L, P;
+  long long n, N;
+  double v;
+  const float* Ip;
+  const float* Im;
+  hipStream_t user = nullptr;
+  hipStream_t exec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  LineArgs la;
+  // workspace (n floats each)
+  float *w = nullptr, *t1 = nullptr, *t2 = nullptr;
+  float *g = nullptr, *hd = nullptr, *ho = nullptr, *x = nullptr, *r = nullptr, *zz = nullptr,
+        *p = nullptr, *q = nullptr;
+  double* partial = nullptr;     // general partial sums
+  double* partial_b = nullptr;   // ADMM b-step (fast + hard kernels)
+  double* partial_e = nullptr;   // ADMM z/u epilogue
+  size_t partial_cap = 0;
+  DevState* st = nullptr;
+  DevState* st_h = nullptr;      // pinned mirror
+  int* hard_list = nullptr;
+  int hard_blocks = 0;
+  // DCT tables (packed MFMA fragments), eigenvalues
+  void *A3f = nullptr, *A3i = nullptr, *A2f = nullptr, *A2i = nullptr;
+  int RT2 = 0, KS2 = 0, RT3 = 0, KS3 = 0;
+  float *lam2 = nullptr, *lam3 = nullptr;
+  double* hist = nullptr;
+  int hist_cap = 0;
+  // captured ADMM chunk
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int g_chunk = 0, g_sqp = 0;
+  float *g_b = nullptr, *g_z = nullptr, *g_u = nullptr;
+};
+
+static void enter(epi_problem* p) {
+  (void)hipEventRecord(p->ev_in, p->user);
+  (void)hipStreamWaitEvent(p->exec, p->ev_in, 0);
+}
+static void leave(epi_problem* p) {
+  (void)hipEventRecord(p->ev_out, p->exec);
+  (void)hipStreamWaitEvent(p->user, p->ev_out, 0);
+}
+
+EPI_API int32_t epi_abi_version(void) { return EPI_ABI_VERSION; }
+
+EPI_API const char* epi_last_error(void) { return g_err.c_str(); }
+
+EPI_API void epi_gn_default_opts(epi_gn_opts* o) {
+  if (!o) return;
+  o->max_iter = 10;
+  o->pcg_max = 30;
+  o->precond = EPI_PRECOND_BLOCK;
+  o->ls_max = 10;
+  o->use_stopping = 1;
+  o->eta = 0.1;
+  o->eps_obj = 1e-3;
+  o->eps_iter = 1e-2;
+  o->eps_grad = 1e-2;
+  o->ls_c1 = 1e-4;
+  o->rel_grad_tol = 0.0;
+}
+
+EPI_API void epi_admm_default_opts(epi_admm_opts* o) {
+  if (!o) return;
+  o->max_iter = 100;
+  o->sqp_iters = 1;
+  o->check_every = 8;
+  o->rho = 1e3;
+  o->eps_abs = 0.2;
+  o->eps_rel = 0.2;
+}
+
+// ------------------------------------------------------------------------------------
+// DCT tables: orthonormal DCT-II C[j'][j] = s_j' cos(pi j' (2j+1) / (2m)) (eq. dctdiag),
+// eigenvalues of D~(m,h)'D~(m,h): (2 - 2 cos(pi j / m)) / h^2.
+// ------------------------------------------------------------------------------------
+static void dct_host(int m, std::vector<double>& C) {
+  C.assign((size_t)m * m, 0.0);
+  for (int a = 0; a < m; ++a) {
+    const double s = (a == 0) ? sqrt(1.0 / m) : sqrt(2.0 / m);
+    for (int j = 0; j < m; ++j) C[(size_t)a * m + j] = s * cos(M_PI * a * (2.0 * j + 1.0) / (2.0 * m));
+  }
+}
+
+static uint16_t bf16_rn(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float bf16_to_f(uint16_t h) {
+  uint32_t u = ((uint32_t)h) << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return x;
+}
+
+// Pack A (m x m, row-major, A[row][k]) into MFMA operand fragments.
+// bf16 (16x16x32): fragment (rt, ks) lane l holds A[16 rt + l%16][32 ks + 8 (l/16) + e], e<8;
+//   hi block followed by the lo block (a = hi + lo).
+// fp32 (16x16x4): fragment (rt, ks) lane l holds A[16 rt + l%16][4 ks + l/16].
+static std::vector<uint16_t> pack_bf16(const std::vector<double>& A, int m, int& RT, int& KS) {
+  RT = (m + 15) / 16;
+  KS = (m + 31) / 32;
+  const size_t nfr = (size_t)RT * KS * 64 * 8;
+  std::vector<uint16_t> out(2 * nfr, 0);
+  for (int rt = 0; rt < RT; ++rt)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+          const int row = 16 * rt + (l & 15), k = 32 * ks + 8 * (l >> 4) + e;
+          const double val = (row < m && k < m) ? A[(size_t)row * m + k] : 0.0;
+          const uint16_t hi = bf16_rn((float)val);
+          const uint16_t lo = bf16_rn((float)(val - (double)bf16_to_f(hi)));
+          const size_t idx = (((size_t)rt * KS + ks) * 64 + l) * 8 + e;
+          out[idx] = hi;
+          out[nfr + idx] = lo;
+        }
+  return out;
+}
+static std::vector<float> pack_f32(const std::vector<double>& A, int m, int& RT, int& KS) {
+  RT = (m + 15) / 16;
+  KS = (m + 3) / 4;
+  std::vector<float> out((size_t)RT * KS * 64, 0.0f);
+  for (int rt = 0; rt < RT; ++rt)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        const int row = 16 * rt + (l & 15), k = 4 * ks + (l >> 4);
+        out[((size_t)rt * KS + ks) * 64 + l] = (row < m && k < m) ? (float)A[(size_t)row * m + k] : 0.0f;
+      }
+  return out;
+}
+
+static epi_status upload_matrix(epi_problem* p, const std::vector<double>& A, int m, void** dst,
+                                int& RT, int& KS) {
+  if (p->grid.precision == EPI_PREC_MIXED) {
+    auto v = pack_bf16(A, m, RT, KS);
+    HIPCHK(hipMalloc(dst, v.size() * sizeof(uint16_t)));
+    HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  } else {
+    auto v = pack_f32(A, m, RT, KS);
+    HIPCHK(hipMalloc(dst, v.size() * sizeof(float)));
+    HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  return EPI_OK;
+}
+
+static epi_status build_tables(epi_problem* p) {
+  std::vector<double> C, Ct;
+  int RT, KS;
+  for (int axis = 2; axis <= 3; ++axis) {
+    const int m = axis == 2 ? p->m2 : p->m3;
+    const double h = p->grid.h[axis - 1];
+    dct_host(m, C);
+    Ct.assign((size_t)m * m, 0.0);
+    for (int a = 0; a < m; ++a)
+      for (int j = 0; j < m; ++j) Ct[(size_t)j * m + a] = C[(size_t)a * m + j];
+    epi_status s;
+    if (axis == 2) {
+      if ((s = upload_matrix(p, C, m, &p->A2f, RT, KS)) != EPI_OK) return s;
+      if ((s = upload_matrix(p, Ct, m, &p->A2i, p->RT2, p->KS2)) != EPI_OK) return s;
+    } else {
+      if ((s = upload_matrix(p, C, m, &p->A3f, RT, KS)) != EPI_OK) return s;
+      if ((s = upload_matrix(p, Ct, m, &p->A3i, p->RT3, p->KS3)) != EPI_OK) return s;
+    }
+    std::vector<float> lam(m);
+    for (int j = 0; j < m; ++j) lam[j] = (float)((2.0 - 2.0 * cos(M_PI * j / m)) / (h * h));
+    float** dl = axis == 2 ? &p->lam2 : &p->lam3;
+    HIPCHK(hipMalloc(dl, m * sizeof(float)));
+    HIPCHK(hipMemcpy(*dl, lam.data(), m * sizeof(float), hipMemcpyHostToDevice));
+  }
+  return EPI_OK;
+}
+
+static void free_graph(epi_problem* p) {
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->gexec = nullptr;
+  p->graph = nullptr;
+  p->g_chunk = 0;
+}
+
+EPI_API void epi_destroy(epi_problem* p) {
+  if (!p) return;
+  if (p->exec) (void)hipStreamSynchronize(p->exec);
+  free_graph(p);
+  void* bufs[] = {p->w, p->t1, p->t2, p->g, p->hd, p->ho, p->x, p->r, p->zz, p->p, p->q,
+                  p->partial, p->partial_b, p->partial_e, p->st, p->hard_list, p->A3f,
+                  p->A3i, p->A2f, p->A2i, p->lam2, p->lam3, p->hist};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (p->st_h) (void)hipHostFree(p->st_h);
+  if (p->ev_in) (void)hipEventDestroy(p->ev_in);
+  if (p->ev_out) (void)hipEventDestroy(p->ev_out);
+  if (p->exec) (void)hipStreamDestroy(p->exec);
+  delete p;
+}
+
+static int dct_tiles_axis3(const epi_problem* p) {
+  const long long Q = (long long)p->m2 * (p->M + 1);
+  return (int)((Q + 63) / 64);
+}
+static int dct_tiles_axis2(const epi_problem* p) { return p->m3 * ((p->M + 1 + 63) / 64); }
+
+static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float* Im, void* stream,
+                             epi_problem** out) {
+  if (!grid || !Ip || !Im || !out) return fail(EPI_EINVAL, "null argument");
+  *out = nullptr;
+  if (grid->ndim != 2 && grid->ndim != 3) return fail(EPI_EINVAL, "ndim must be 2 or 3");
+  const int M = grid->m[0], m2 = grid->m[1], m3 = grid->m[2];
+  if (M < 2 || m2 < 1 || m3 < 1) return fail(EPI_EINVAL, "cell counts must be M >= 2, m2, m3 >= 1");
+  if (grid->ndim == 2 && m3 != 1) return fail(EPI_EINVAL, "2D problems need m[2] = 1");
+  if (M + 1 > 64 * EPI_PMAX) return fail(EPI_EINVAL, "M + 1 = %d exceeds %d faces per PE line", M + 1, 64 * EPI_PMAX);
+  if (m2 > 256 || m3 > 256) return fail(EPI_EINVAL, "m2, m3 must be <= 256 (DCT axes)");
+  for (int a = 0; a < 3; ++a)
+    if (!(grid->h[a] > 0.0)) return fail(EPI_EINVAL, "h[%d] must be > 0", a);
+  if (!(grid->alpha >= 0.0) || !(grid->beta >= 0.0) || !(grid->gamma >= 0.0))
+    return fail(EPI_EINVAL, "alpha, beta, gamma must be >= 0");
+  if (grid->precision != EPI_PREC_FP32 && grid->precision != EPI_PREC_MIXED)
+    return fail(EPI_EINVAL, "unknown precision %d", grid->precision);
+
+  epi_problem* p = new epi_problem();
+  p->grid = *grid;
+  p->M = M;
+  p->m2 = m2;
+  p->m3 = m3;
+  p->L = m2 * m3;
+  p->P = (M + 1 + 63) / 64;
+  p->n = (long long)(M + 1) * p->L;
+  p->N = (long long)M * p->L;
+  p->v = grid->h[0] * grid->h[1] * grid->h[2];
+  p->Ip = Ip;
+  p->Im = Im;
+  p->user = (hipStream_t)stream;
+  LineArgs& a = p->la;
+  a.Ip = Ip;
+  a.Im = Im;
+  a.M = M;
+  a.m2 = m2;
+  a.m3 = m3;
+  a.L = p->L;
+  a.hp = (float)grid->h[0];
+  a.inv_hp = (float)(1.0 / grid->h[0]);
+  a.inv_h2sq = (float)(1.0 / (grid->h[1] * grid->h[1]));
+  a.inv_h3sq = (float)(1.0 / (grid->h[2] * grid->h[2]));
+  a.v = (float)p->v;
+  a.alpha = (float)grid->alpha;
+  a.beta = (float)grid->beta;
+  a.gamma = (float)grid->gamma;
+  a.nblk = line_blocks(a);
+  *out = p;
+
+  static bool lds_set = false;
+  if (!lds_set) {
+    // a failure here only matters for tiles above 64 KB, whose launches then report it
+    (void)dct_set_lds_limits();
+    lds_set = true;
+  }
+  (void)hipGetLastError();
+  HIPCHK(hipStreamCreateWithFlags(&p->exec, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
+  const size_t nb = (size_t)p->n * sizeof(float);
+  float** bufs[] = {&p->w, &p->t1, &p->t2, &p->g, &p->hd, &p->ho, &p->x, &p->r, &p->zz, &p->p, &p->q};
+  for (float** b : bufs) HIPCHK(hipMalloc(b, nb));
+  const int lb = line_blocks(a);
+  p->hard_blocks = p->L < 1024 ? p->L : 1024;
+  size_t cap = (size_t)lb * NQ_EVAL;
+  cap = std::max(cap, (size_t)2048 * 2);
+  cap = std::max(cap, (size_t)std::max(dct_tiles_axis2(p), dct_tiles_axis3(p)) * 4);
+  p->partial_cap = cap;
+  HIPCHK(hipMalloc(&p->partial, cap * sizeof(double)));
+  HIPCHK(hipMalloc(&p->partial_b, ((size_t)lb + p->hard_blocks) * sizeof(double)));
+  HIPCHK(hipMalloc(&p->partial_e, (size_t)std::max(dct_tiles_axis2(p), dct_tiles_axis3(p)) * 4 * sizeof(double)));
+  HIPCHK(hipMalloc(&p->st, sizeof(DevState)));
+  HIPCHK(hipHostMalloc((void**)&p->st_h, sizeof(DevState), hipHostMallocDefault));
+  memset(p->st_h, 0, sizeof(DevState));
+  HIPCHK(hipMemcpy(p->st, p->st_h, sizeof(DevState), hipMemcpyHostToDevice));
+  HIPCHK(hipMalloc(&p->hard_list, (size_t)p->L * sizeof(int)));
+  epi_status s = build_tables(p);
+  if (s != EPI_OK) return s;
+
+  // the images must be finite
+  enter(p);
+  launch_count_nonfinite(p->exec, p->N, Ip, p->partial);
+  launch_count_nonfinite(p->exec, p->N, Im, p->partial + flat_blocks(p->N));
+  CHKLAUNCH();
+  FinArgs f{};
+  f.kind = FIN_DOT;
+  f.partial = p->partial;
+  f.nb1 = 2 * flat_blocks(p->N);
+  launch_finalize(p->exec, f, p->st);
+  CHKLAUNCH();
+  HIPCHK(hipMemcpyAsync(p->st_h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+  HIPCHK(hipStreamSynchronize(p->exec));
+  leave(p);
+  if (p->st_h->gTd != 0.0) return fail(EPI_ENUMERIC, "images contain %.0f non-finite values", p->st_h->gTd);
+  return EPI_OK;
+}
+
+EPI_API epi_status epi_setup(const epi_grid* grid, const float* d_Iplus, const float* d_Iminus,
+                                void* stream, epi_problem** out) {
+  epi_status s = setup_impl(grid, d_Iplus, d_Iminus, stream, out);
+  if (s != EPI_OK && out && *out) {
+    epi_destroy(*out);
+    *out = nullptr;
+  }
+  return s;
+}
+
+// ------------------------------------------------------------------------------------
+// objective (eq. D, eq. S, eq. P and their gradients)
+// ------------------------------------------------------------------------------------
+static epi_status eval_terms(epi_problem* p, const float* b, int mode, int with_pen, float* grad) {
+  launch_eval(p->exec, p->P, mode, p->la, b, nullptr, 0, with_pen, grad, p->hd, p->ho,
+              p->partial, p->st);
+  CHKLAUNCH();
+  FinArgs f{};
+  f.kind = FIN_EVAL;
+  f.partial = p->partial;
+  f.nb1 = line_blocks(p->la);
+  f.v = p->v;
+  launch_finalize(p->exec, f, p->st);
+  CHKLAUNCH();
+  return EPI_OK;
+}
+
+static void terms_from_state(const epi_problem* p, const DevState* s, int with_pen, epi_terms* t) {
+  t->D = s->evalD;
+  t->S = 0.5 * p->v * (s->evalS1 + s->evalSx);
+  t->feasible = s->eval_infeasible == 0;
+  if (with_pen)
+    t->P = t->feasible ? p->grid.beta * p->v * s->evalP : INFINITY;
+  else
+    t->P = 0.0;
+  t->J = t->D + p->grid.alpha * t->S + t->P;
+}
+
+EPI_API epi_status epi_objective(epi_problem* p, const float* d_b, int32_t with_penalty,
+                                    epi_terms* out, float* d_grad) {
+  if (!p || !d_b || !out) return fail(EPI_EINVAL, "null argument");
+  enter(p);
+  epi_status s = eval_terms(p, d_b, d_grad ? 1 : 0, with_penalty ? 1 : 0, d_grad);
+  if (s != EPI_OK) return s;
+  HIPCHK(hipMemcpyAsync(p->st_h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+  HIPCHK(hipStreamSynchronize(p->exec));
+  leave(p);
+  terms_from_state(p, p->st_h, with_penalty, out);
+  if (!(out->D == out->D) || !(out->S == out->S)) return fail(EPI_ENUMERIC, "objective is NaN");
+  return EPI_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// z-step passes
+// ------------------------------------------------------------------------------------
+static GemmArgs gemm_axis3(const epi_problem* p, const float* in, float* out, const void* A) {
+  GemmArgs g{};
+  g.in = in;
+  g.out = out;
+  g.rows = p->m3;
+  g.ncol = p->m2 * (p->M + 1);
+  g.ld = (long long)p->m2 * (p->M + 1);
+  g.bstride = 0;
+  g.nbatch = 1;
+  g.col_tiles = (g.ncol + 63) / 64;
+  g.RT = p->RT3;
+  g.KS = p->KS3;
+  g.A1 = A;
+  g.A2 = nullptr;
+  g.alpha = (float)p->grid.alpha;
+  g.st = p->st;
+  return g;
+}
+static GemmArgs gemm_axis2(const epi_problem* p, const float* in, float* out) {
+  GemmArgs g{};
+  g.in = in;
+  g.out = out;
+  g.rows = p->m2;
+  g.ncol = p->M + 1;
+  g.ld = p->M + 1;
+  g.bstride = (long long)p->m2 * (p->M + 1);
+  g.nbatch = p->m3;
+  g.col_tiles = (g.ncol + 63) / 64;
+  g.RT = p->RT2;
+  g.KS = p->KS2;
+  g.A1 = p->A2f;
+  g.A2 = p->A2i;
+  g.lam_row = p->lam2;
+  g.lam_batch = p->lam3;
+  g.alpha = (float)p->grid.alpha;
+  g.st = p->st;
+  return g;
+}
+
+// z = smoothness solve of w; with admm != 0 the last pass performs the u-step epilogue
+// (reads b, u, z; writes z, u; partial sums into partial_e).
+static epi_status launch_zstep(epi_problem* p, const float* w, float* z, int admm, const float* b,
+                               float* u) {
+  const int prec = p->grid.precision;
+  const int* done = admm ? &p->st->admm_done : nullptr;
+  if (p->m3 == 1) {
+    GemmArgs g2 = gemm_axis2(p, w, z);
+    g2.done = done;
+    if (admm) {
+      g2.epi = 1;
+      g2.b = b;
+      g2.z = z;
+      g2.u = u;
+      g2.partial = p->partial_e;
+    }
+    launch_dct_axis2_fused(p->exec, prec, g2);
+    CHKLAUNCH();
+    return EPI_OK;
+  }
+  GemmArgs g1 = gemm_axis3(p, w, p->t1, p->A3f);
+  g1.done = done;
+  launch_dct_axis3(p->exec, prec, g1);
+  CHKLAUNCH();
+  GemmArgs g2 = gemm_axis2(p, p->t1, p->t2);
+  g2.done = done;
+  launch_dct_axis2_fused(p->exec, prec, g2);
+  CHKLAUNCH();
+  GemmArgs g3 = gemm_axis3(p, p->t2, z, p->A3i);
+  g3.done = done;
+  if (admm) {
+    g3.epi = 1;
+    g3.b = b;
+    g3.z = z;
+    g3.u = u;
+    g3.partial = p->partial_e;
+  }
+  launch_dct_axis3(p->exec, prec, g3);
+  CHKLAUNCH();
+  return EPI_OK;
+}
+
+static int zstep_epi_blocks(const epi_problem* p) {
+  return p->m3 == 1 ? dct_tiles_axis2(p) : dct_tiles_axis3(p);
+}
+
+EPI_API epi_status epi_smooth_solve(epi_problem* p, const float* d_w, double rho, float* d_z) {
+  if (!p || !d_w || !d_z) return fail(EPI_EINVAL, "null argument");
+  if (!(rho > 0.0)) return fail(EPI_EINVAL, "rho must be > 0");
+  enter(p);
+  HIPCHK(hipStreamSynchronize(p->exec));   // the pinned mirror is reused below
+  p->st_h->rho = rho;
+  HIPCHK(hipMemcpyAsync(&p->st->rho, &p->st_h->rho, sizeof(double), hipMemcpyHostToDevice, p->exec));
+  epi_status s = launch_zstep(p, d_w, d_z, 0, nullptr, nullptr);
+  if (s != EPI_OK) return s;
+  HIPCHK(hipStreamSynchronize(p->exec));
+  leave(p);
+  return EPI_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// ADMM (Section 4.2)
+// ------------------------------------------------------------------------------------
+static epi_status admm_iteration(epi_problem* p, float* b, float* z, float* u, int sqp) {
+  const int lb = line_blocks(p->la);
+  for (int s = 0; s < sqp; ++s) {
+    if (s > 0) {
+      FinArgs f{};
+      f.kind = FIN_HARD_RESET;
+      launch_finalize(p->exec, f, p->st);
+    }
+    launch_admm_bstep(p->exec, p->P, p->la, b, z, u, p->w, p->hard_list, p->partial_b, p->st,
+                      p->hard_blocks);
+    CHKLAUNCH();
+  }
+  epi_status st = launch_zstep(p, p->w, z, 1, b, u);
+  if (st != EPI_OK) return st;
+  FinArgs f{};
+  f.kind = FIN_ADMM;
+  f.partial = p->partial_b;
+  f.nb1 = lb;
+  f.partial2 = p->partial_b + lb;
+  f.nb2 = p->hard_blocks;
+  f.partial3 = p->partial_e;
+  f.nb3 = zstep_epi_blocks(p);
+  f.hist = p->hist;
+  f.hist_len = p->hist_cap;
+  launch_finalize(p->exec, f, p->st);
+  CHKLAUNCH();
+  return EPI_OK;
+}
+
+static epi_status count_violations(epi_problem* p, const float* b, float thr, double* count) {
+  launch_count_violations(p->exec, p->la, b, thr, p->partial);
+  CHKLAUNCH();
+  FinArgs f{};
+  f.kind = FIN_DOT;
+  f.partial = p->partial;
+  f.nb1 = flat_blocks(p->N);
+  launch_finalize(p->exec, f, p->st);
+  CHKLAUNCH();
+  HIPCHK(hipMemcpyAsync(p->st_h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+  HIPCHK(hipStreamSynchronize(p->exec));
+  *count = p->st_h->gTd;
+  return EPI_OK;
+}
+
+EPI_API epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
+                                     const epi_admm_opts* opts, epi_admm_report* rep) {
+  if (!p || !d_b || !d_z || !d_u || !opts) return fail(EPI_EINVAL, "null argument");
+  if (!(opts->rho > 0.0)) return fail(EPI_EINVAL, "rho must be > 0");
+  if (opts->max_iter < 0 || opts->sqp_iters < 1 || opts->check_every < 1)
+    return fail(EPI_EINVAL, "max_iter >= 0, sqp_iters >= 1, check_every >= 1 required");
+  enter(p);
+  double viol = 0.0;
+  epi_status s = count_violations(p, d_b, 1.0f + 1e-5f, &viol);
+  if (s != EPI_OK) return s;
+  if (viol > 0.0) {
+    leave(p);
+    return fail(EPI_EINFEASIBLE, "starting field has %.0f cells with |D1 b| > 1", viol);
+  }
+  const int cap = opts->max_iter > 0 ? opts->max_iter : 1;
+  if (cap > p->hist_cap) {
+    if (p->hist) HIPCHK(hipFree(p->hist));
+    p->hist = nullptr;
+    HIPCHK(hipMalloc(&p->hist, (size_t)4 * cap * sizeof(double)));
+    p->hist_cap = cap;
+    free_graph(p);   // the finalize node holds the history pointer
+  }
+  DevState* h = p->st_h;
+  memset(h, 0, sizeof(DevState));
+  h->rho = opts->rho;
+  h->eps_abs = opts->eps_abs;
+  h->eps_rel = opts->eps_rel;
+  h->sqrt_n = sqrt((double)p->n);
+  h->v = p->v;
+  h->admm_max = opts->max_iter;
+  h->admm_done = opts->max_iter == 0 ? 2 : 0;
+  HIPCHK(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->exec));
+
+  const int chunk = opts->check_every;
+  const bool use_graph = true;
+  if (use_graph && (p->g_chunk != chunk || p->g_sqp != opts->sqp_iters || p->g_b != d_b ||
+                    p->g_z != d_z || p->g_u != d_u)) {
+    free_graph(p);
+    HIPCHK(hipStreamBeginCapture(p->exec, hipStreamCaptureModeThreadLocal));
+    for (int i = 0; i < chunk; ++i) {
+      s = admm_iteration(p, d_b, d_z, d_u, opts->sqp_iters);
+      if (s != EPI_OK) {
+        hipGraph_t tmp = nullptr;
+        (void)hipStreamEndCapture(p->exec, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        return s;
+      }
+    }
+    HIPCHK(hipStreamEndCapture(p->exec, &p->graph));
+    HIPCHK(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+    p->g_chunk = chunk;
+    p->g_sqp = opts->sqp_iters;
+    p->g_b = d_b;
+    p->g_z = d_z;
+    p->g_u = d_u;
+  }
+  int done = opts->max_iter == 0;
+  int launched = 0;
+  while (!done) {
+    HIPCHK(hipGraphLaunch(p->gexec, p->exec));
+    launched += chunk;
+    HIPCHK(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+    HIPCHK(hipStreamSynchronize(p->exec));
+    done = h->admm_done != 0 || launched >= opts->max_iter;
+  }
+  HIPCHK(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+  HIPCHK(hipStreamSynchronize(p->exec));
+  const int iters = h->admm_iter;
+  if (rep) {
+    rep->iters = iters;
+    rep->converged = h->admm_done == 1 && h->numeric_bad == 0;
+    rep->max_active = h->max_active;
+    rep->hard_lines = h->hard_total;
+    rep->status = h->numeric_bad ? EPI_ENUMERIC : EPI_OK;
+    double* outs[4] = {rep->r_pri, rep->r_dual, rep->eps_pri, rep->eps_dual};
+    for (int k = 0; k < 4; ++k)
+      if (outs[k] && iters > 0)
+        HIPCHK(hipMemcpy(outs[k], p->hist + (size_t)k * p->hist_cap, iters * sizeof(double),
+                         hipMemcpyDeviceToHost));
+  }
+  leave(p);
+  if (h->numeric_bad) return fail(EPI_ENUMERIC, "non-finite value during ADMM");
+  return EPI_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// GN-PCG (Section 4.1)
+// ------------------------------------------------------------------------------------
+EPI_API epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts* opts,
+                                      epi_gn_report* rep) {
+  if (!p || !d_b || !opts) return fail(EPI_EINVAL, "null argument");
+  if (opts->max_iter < 0 || opts->pcg_max < 0 || opts->ls_max < 1 || opts->precond < 0 ||
+      opts->precond > 2 || !(opts->eta > 0.0))
+    return fail(EPI_EINVAL, "invalid GN options");
+  enter(p);
+  const long long n = p->n;
+  const int lb = line_blocks(p->la);
+  DevState* h = p->st_h;
+  HIPCHK(hipStreamSynchronize(p->exec));
+  memset(h, 0, sizeof(DevState));
+  h->eta2 = opts->eta * opts->eta;
+  h->c1 = opts->ls_c1;
+  HIPCHK(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->exec));
+  epi_status s = eval_terms(p, d_b, 2, 1, p->g);
+  if (s != EPI_OK) return s;
+  HIPCHK(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+  HIPCHK(hipStreamSynchronize(p->exec));
+  epi_terms t;
+  terms_from_state(p, h, 1, &t);
+  if (!t.feasible) {
+    leave(p);
+    return fail(EPI_EINFEASIBLE, "starting field has %d cells with |D1 b| >= 1", h->eval_infeasible);
+  }
+  if (!(t.J == t.J)) return fail(EPI_ENUMERIC, "objective is NaN at the starting field");
+  double J = t.J, J0 = t.J;
+  double gn = sqrt(h->evalG2), g0 = gn;
+  if (rep) {
+    rep->iters = 0;
+    rep->converged = 0;
+    rep->ls_failed = 0;
+    rep->status = EPI_OK;
+    if (rep->J) rep->J[0] = J;
+    if (rep->grad_norm) rep->grad_norm[0] = gn;
+  }
+  double Jprev = 0.0, dstep = 0.0, bprev = 0.0;
+  bool converged = false, ls_failed = false;
+  int k = 0;
+  for (;; ++k) {
+    if (k > 0 && opts->use_stopping) {
+      const bool c1 = fabs(J - Jprev) <= opts->eps_obj * (1.0 + fabs(J0));
+      const bool c2 = dstep <= opts->eps_iter * (1.0 + bprev);
+      const bool c3 = gn <= opts->eps_grad * (1.0 + fabs(J0));
+      if (c1 && c2 && c3) {
+        converged = true;
+        break;
+      }
+    }
+    if (opts->rel_grad_tol > 0.0 && gn <= opts->rel_grad_tol * g0) {
+      converged = true;
+      break;
+    }
+    if (k >= opts->max_iter) break;
+    // PCG on H d = -g, the hessian blocks are in hd/ho from the last evaluation
+    launch_pcg_init(p->exec, p->P, p->la, opts->precond, p->g, p->hd, p->ho, p->x, p->r, p->zz,
+                    p->p, p->partial);
+    CHKLAUNCH();
+    FinArgs f{};
+    f.partial = p->partial;
+    f.v = p->v;
+    f.alpha = p->grid.alpha;
+    f.beta = p->grid.beta;
+    f.kind = FIN_PCG_INIT;
+    f.nb1 = lb;
+    launch_finalize(p->exec, f, p->st);
+    for (int it = 0; it < opts->pcg_max; ++it) {
+      launch_matvec(p->exec, p->la, p->p, p->hd, p->ho, p->q, p->partial, p->st);
+      f.kind = FIN_PCG_ALPHA;
+      f.nb1 = flat_blocks(n);
+      launch_finalize(p->exec, f, p->st);
+      launch_pcg_update(p->exec, p->P, p->la, opts->precond, p->hd, p->ho, p->x, p->r, p->zz,
+                        p->p, p->q, p->partial, p->st);
+      f.kind = FIN_PCG_UPDATE;
+      f.nb1 = lb;
+      launch_finalize(p->exec, f, p->st);
+      launch_pupdate(p->exec, n, p->zz, p->p, p->st);
+      CHKLAUNCH();
+      if ((it & 3) == 3 && it + 1 < opts->pcg_max) {
+        HIPCHK(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+        HIPCHK(hipStreamSynchronize(p->exec));
+        if (h->pcg_done) break;
+      }
+    }
+    // Armijo line search on J_GN along d = x
+    launch_dot(p->exec, n, p->g, p->x, p->partial);
+    f.kind = FIN_DOT;
+    f.nb1 = flat_blocks(n);
+    launch_finalize(p->exec, f, p->st);
+    f.kind = FIN_LS_INIT;
+    f.value = J;
+    launch_finalize(p->exec, f, p->st);
+    for (int t2 = 0; t2 < opts->ls_max; ++t2) {
+      launch_eval(p->exec, p->P, 0, p->la, d_b, p->x, t2, 1, nullptr, nullptr, nullptr,
+                  p->partial, p->st);
+      f.kind = FIN_LS;
+      f.nb1 = lb;
+      f.trial = t2;
+      launch_finalize(p->exec, f, p->st);
+    }
+    launch_gn_step(p->exec, n, d_b, p->x, p->partial, p->st);
+    f.kind = FIN_STEP;
+    f.nb1 = flat_blocks(n);
+    launch_finalize(p->exec, f, p->st);
+    CHKLAUNCH();
+    s = eval_terms(p, d_b, 2, 1, p->g);
+    if (s != EPI_OK) return s;
+    HIPCHK(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+    HIPCHK(hipStreamSynchronize(p->exec));
+    const double lam = h->lam_acc;
+    if (rep) {
+      if (rep->pcg_iters) rep->pcg_iters[k] = h->pcg_iters;
+      if (rep->pcg_relres) rep->pcg_relres[k] = h->relres;
+      if (rep->step) rep->step[k] = lam;
+      rep->iters = k + 1;
+    }
+    if (!(lam > 0.0)) {
+      ls_failed = true;
+      break;
+    }
+    Jprev = J;
+    terms_from_state(p, h, 1, &t);
+    J = t.J;
+    gn = sqrt(h->evalG2);
+    dstep = sqrt(h->step2);
+    bprev = sqrt(h->bold2);
+    if (rep) {
+      if (rep->J) rep->J[k + 1] = J;
+      if (rep->grad_norm) rep->grad_norm[k + 1] = gn;
+    }
+    if (!(J == J) || !(gn == gn)) {
+      leave(p);
+      return fail(EPI_ENUMERIC, "non-finite objective in GN iteration %d", k);
+    }
+  }
+  if (rep) {
+    rep->converged = converged;
+    rep->ls_failed = ls_failed;
+  }
+  leave(p);
+  return EPI_OK;
+}

@@ -1,0 +1,229 @@
+// Device-side building blocks shared by the kernels of the EPI solver library (gfx950).
+//
+// Wavefronts are 64 lanes. A PE line with M + 1 faces is owned by one wavefront: lane l
+// holds the P consecutive faces [P l, P l + P) in registers (P = ceil((M + 1) / 64)), and
+// cell c (between faces c and c + 1) lives with face c. Rows beyond the line are padding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "epi_common.hpp"
+
+namespace epi {
+
+// ------------------------------------------------------------------------------------
+// Shuffles and reductions within one wavefront
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ float shfl_up0(float v, int d, int lane) {
+  float t = __shfl_up(v, d, EPI_WAVE);
+  return lane >= d ? t : 0.0f;
+}
+__device__ __forceinline__ float shfl_down0(float v, int d, int lane) {
+  float t = __shfl_down(v, d, EPI_WAVE);
+  return lane + d < EPI_WAVE ? t : 0.0f;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, EPI_WAVE);
+  return v;
+}
+__device__ __forceinline__ float wave_maxf(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, EPI_WAVE));
+  return v;
+}
+__device__ __forceinline__ int wave_sumi(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, EPI_WAVE);
+  return v;
+}
+
+// Sum NQ float64 values over the workgroup and store them at partial[blockIdx.x*NQ + q].
+// Every thread of the block must call it (it contains a barrier).
+template <int NQ>
+__device__ __forceinline__ void block_partials(double (&v)[NQ], double* partial, int slot) {
+  __shared__ double sh[NQ][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double s = wave_sum(v[q]);
+    if (lane == 0) sh[q][wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NQ) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[threadIdx.x][w];
+    partial[(size_t)slot * NQ + threadIdx.x] = s;
+  }
+}
+
+// Deterministic sum of partial[b*NQ + q] over b in [0, nb) by one 256-thread block;
+// returns the sums to every thread via out_sh (fixed summation order).
+template <int NQ>
+__device__ __forceinline__ void reduce_partials(const double* partial, int nb, double* out_sh) {
+  __shared__ double red[NQ][256];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double s = 0.0;
+    for (int b = t; b < nb; b += blockDim.x) s += partial[(size_t)b * NQ + q];
+    red[q][t] = s;
+  }
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) red[q][t] += red[q][t + w];
+    }
+    __syncthreads();
+  }
+  if (t < NQ) out_sh[t] = red[t][0];
+  __syncthreads();
+}
+
+// Workgroups are dealt round-robin over the 8 XCDs; remap so that each XCD (and its L2)
+// walks one contiguous range of logical block indices.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+  const int nx = 8;
+  const int q = nblk / nx, r = nblk % nx;
+  const int x = bid % nx, k = bid / nx;
+  // XCD x owns logical blocks [x*q + min(x,r), ... ) of size q + (x < r)
+  const int base = x * q + (x < r ? x : r);
+  return base + k;
+}
+
+// ------------------------------------------------------------------------------------
+// LDS staging of one PE line per wavefront (coalesced global access, blocked registers)
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int lds_pad(int t) { return t + (t >> 5); }
+
+template <int P>
+struct LineBuf {
+  static constexpr int SIZE = 64 * P + 2 * P + 2;
+};
+
+// Global -> registers: dst[j] = src[P*lane + j] for P*lane + j < count, else 0.
+template <int P>
+__device__ __forceinline__ void stage_in(const float* __restrict__ src, int count, bool valid,
+                                         float* lds, float (&dst)[P], int lane) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int t = lane + 64 * j;
+    lds[lds_pad(t)] = (valid && t < count) ? src[t] : 0.0f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < P; ++j) dst[j] = lds[lds_pad(P * lane + j)];
+  __syncthreads();
+}
+
+// Registers -> global: dst[P*lane + j] = v[j] for indices < count.
+template <int P>
+__device__ __forceinline__ void stage_out(float* __restrict__ dst, int count, bool valid,
+                                          float* lds, const float (&v)[P], int lane) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) lds[lds_pad(P * lane + j)] = v[j];
+  __syncthreads();
+  if (valid) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int t = lane + 64 * j;
+      if (t < count) dst[t] = lds[lds_pad(t)];
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------------------------
+// Symmetric tridiagonal solve over one wavefront.
+//   row i: e[i-1] x[i-1] + d[i] x[i] + e[i] x[i+1] = r[i]
+// Lane l holds rows [P l, P l + P) in d[], e[], r[] (e[j] couples local rows j and j+1,
+// the last one couples to the next lane). Padding rows must be d = 1, e = 0, r = 0 and
+// the last real row must have e = 0. On return r[] holds x.
+// Method: each lane eliminates its block downwards (Thomas), then upwards, expressing
+// every row through the last unknown of the previous lane and its own last unknown; the
+// resulting 64-row tridiagonal system of block-last unknowns is solved by parallel
+// cyclic reduction across lanes; the interior rows follow by substitution.
+// ------------------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ void wave_tridiag_solve(const float (&d)[P], const float (&e)[P],
+                                                   float (&r)[P], int lane) {
+  float ap[P], cp[P], rp[P];
+  const float a0 = shfl_up0(e[P - 1], 1, lane);   // coupling of row P*lane to the row before
+  {
+    const float inv = 1.0f / d[0];
+    ap[0] = a0 * inv;
+    cp[0] = e[0] * inv;
+    rp[0] = r[0] * inv;
+  }
+#pragma unroll
+  for (int j = 1; j < P; ++j) {
+    const float a = e[j - 1];
+    const float inv = 1.0f / (d[j] - a * cp[j - 1]);
+    ap[j] = -a * ap[j - 1] * inv;
+    cp[j] = e[j] * inv;
+    rp[j] = (r[j] - a * rp[j - 1]) * inv;
+  }
+  // x_j = R_j - A_j X_prev - C_j X_own
+  float R[P], A[P], C[P];
+  R[P - 1] = 0.0f;
+  A[P - 1] = 0.0f;
+  C[P - 1] = -1.0f;
+#pragma unroll
+  for (int j = P - 2; j >= 0; --j) {
+    R[j] = rp[j] - cp[j] * R[j + 1];
+    A[j] = ap[j] - cp[j] * A[j + 1];
+    C[j] = -cp[j] * C[j + 1];
+  }
+  // reduced row of this lane: ap X_{l-1} + X_l + cp x_{first of l+1} = rp (last local row)
+  const float Rn = shfl_down0(R[0], 1, lane);
+  const float An = shfl_down0(A[0], 1, lane);
+  const float Cn = shfl_down0(C[0], 1, lane);
+  float ra = (lane == 0) ? 0.0f : ap[P - 1];
+  float rb = 1.0f - cp[P - 1] * An;
+  float rc = (lane == 63) ? 0.0f : -cp[P - 1] * Cn;
+  float rr = rp[P - 1] - cp[P - 1] * Rn;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) {
+    const bool hasm = lane >= s, hasp = lane + s < 64;
+    float am = __shfl_up(ra, s, 64), bm = __shfl_up(rb, s, 64), cm = __shfl_up(rc, s, 64),
+          xm = __shfl_up(rr, s, 64);
+    float aq = __shfl_down(ra, s, 64), bq = __shfl_down(rb, s, 64), cq = __shfl_down(rc, s, 64),
+          xq = __shfl_down(rr, s, 64);
+    if (!hasm) { am = 0.0f; bm = 1.0f; cm = 0.0f; xm = 0.0f; }
+    if (!hasp) { aq = 0.0f; bq = 1.0f; cq = 0.0f; xq = 0.0f; }
+    const float al = -ra / bm, ga = -rc / bq;
+    const float na = al * am, nc = ga * cq;
+    const float nb = rb + al * cm + ga * aq;
+    const float nr = rr + al * xm + ga * xq;
+    ra = na; rb = nb; rc = nc; rr = nr;
+  }
+  const float X = rr / rb;
+  const float Xp = shfl_up0(X, 1, lane);
+#pragma unroll
+  for (int j = 0; j < P; ++j) r[j] = R[j] - A[j] * Xp - C[j] * X;
+}
+
+// ------------------------------------------------------------------------------------
+// Penalty phi (eq. P) and its derivatives (eq. dphi), |x| < 1
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ float phi_f(float x) {
+  const float q = (1.0f - x) * (1.0f + x);
+  const float x2 = x * x;
+  return x2 * x2 / q;
+}
+__device__ __forceinline__ float dphi_f(float x) {
+  const float q = (1.0f - x) * (1.0f + x);
+  const float x2 = x * x;
+  return (4.0f - 2.0f * x2) * x2 * x / (q * q);
+}
+__device__ __forceinline__ float d2phi_f(float x) {
+  const float q = (1.0f - x) * (1.0f + x);
+  const float x2 = x * x;
+  return 2.0f * x2 * (x2 * x2 - 3.0f * x2 + 6.0f) / (q * q * q);
+}
+
+}  // namespace epi

@@ -1,0 +1,72 @@
+// Host-side launchers of the kernels (one translation unit per kernel family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "epi_common.hpp"
+
+namespace epi {
+
+int line_blocks(const LineArgs& a);
+
+// epi_line.hip
+void launch_eval(hipStream_t s, int P, int mode, LineArgs a, const float* b, const float* d,
+                 int trial, int with_pen, float* grad, float* hdiag, float* hoff,
+                 double* partial, const DevState* st);
+void launch_pcg_init(hipStream_t s, int P, LineArgs a, int precond, const float* grad,
+                     const float* hdiag, const float* hoff, float* x, float* r, float* z,
+                     float* p, double* partial);
+void launch_pcg_update(hipStream_t s, int P, LineArgs a, int precond, const float* hdiag,
+                       const float* hoff, float* x, float* r, float* z, const float* p,
+                       const float* q, double* partial, const DevState* st);
+void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* z,
+                       const float* u, float* w, int* hard_list, double* partial,
+                       DevState* st, int hard_blocks);
+
+// epi_vec.hip
+int flat_blocks(long long n);
+void launch_matvec(hipStream_t s, LineArgs a, const float* p, const float* hdiag,
+                   const float* hoff, float* q, double* partial, const DevState* st);
+void launch_pupdate(hipStream_t s, long long n, const float* z, float* p, const DevState* st);
+void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial);
+void launch_gn_step(hipStream_t s, long long n, float* b, const float* d, double* partial,
+                    const DevState* st);
+void launch_count_violations(hipStream_t s, LineArgs a, const float* b, float thr,
+                             double* partial);
+void launch_count_nonfinite(hipStream_t s, long long n, const float* x, double* partial);
+
+// single-block finalisation kernels
+enum FinKind : int {
+  FIN_EVAL = 0,        // -> st->eval*
+  FIN_PCG_INIT = 1,    // rz, rhs2
+  FIN_PCG_ALPHA = 2,   // alpha = rz / pq
+  FIN_PCG_UPDATE = 3,  // relres, beta, done
+  FIN_DOT = 4,         // gTd
+  FIN_LS = 5,          // Armijo test of one trial
+  FIN_STEP = 6,        // |lam d|^2, |b_old|^2
+  FIN_ADMM = 7,        // residuals, tolerances, stopping flag, history
+  FIN_LS_INIT = 8,     // J0 = value; clear the line-search state
+  FIN_HARD_RESET = 9   // fold hard_count into hard_total between SQP linearisations
+};
+struct FinArgs {
+  int kind;
+  const double* partial;
+  int nb1;           // blocks of the first partial range
+  int nb2;           // blocks of the second range (ADMM: hard-line kernel)
+  const double* partial2;
+  int nb3;
+  const double* partial3;
+  int trial;
+  double v, alpha, beta;
+  double* hist;      // ADMM history base (4 arrays of hist_len)
+  int hist_len;
+  double value;
+};
+void launch_finalize(hipStream_t s, const FinArgs& f, DevState* st);
+
+// epi_dct.hip
+void launch_dct_axis3(hipStream_t s, int prec, const GemmArgs& g);
+void launch_dct_axis2_fused(hipStream_t s, int prec, const GemmArgs& g);
+int dct_set_lds_limits();
+
+}  // namespace epi

@@ -1,0 +1,301 @@
+// Flat (face-parallel) kernels and the single-block finalisation kernels.
+#include <math.h>
+
+#include "epi_device.hpp"
+#include "epi_common.hpp"
+#include "epi_launch.hpp"
+
+namespace epi {
+
+int flat_blocks(long long n) {
+  long long b = (n + 2047) / 2048;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// Contiguous chunk of a flat index range owned by this workgroup (XCD-aware order).
+__device__ __forceinline__ void chunk_of(long long n, long long& lo, long long& hi) {
+  const int nb = gridDim.x;
+  const int lb = xcd_remap(blockIdx.x, nb);
+  const long long per = (n + nb - 1) / nb;
+  lo = (long long)lb * per;
+  hi = lo + per < n ? lo + per : n;
+}
+
+// q = H_JGN p = (line tridiagonal) p + alpha v (D2'D2 + D3'D3) p  (eq. dJGN, Section 3:
+// the transverse coupling of the regulariser is a Neumann Laplacian stencil); partial p.q
+__global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restrict__ p,
+                                                const float* __restrict__ hd,
+                                                const float* __restrict__ ho,
+                                                float* __restrict__ q, double* partial,
+                                                const DevState* st) {
+  if (st->pcg_done) return;
+  const int NF = a.M + 1;
+  const long long n = (long long)NF * a.L;
+  const long long plane = (long long)NF * a.m2;
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  const float av = a.alpha * a.v;
+  double acc[1] = {0.0};
+  for (long long f = lo + threadIdx.x; f < hi; f += blockDim.x) {
+    const int i = (int)(f % NF);
+    const long long line = f / NF;
+    const int jj = (int)(line % a.m2), kk = (int)(line / a.m2);
+    const float pc = p[f];
+    float y = hd[f] * pc;
+    if (i > 0) y = fmaf(ho[f - 1], p[f - 1], y);
+    if (i < NF - 1) y = fmaf(ho[f], p[f + 1], y);
+    float l2 = 0.0f, l3 = 0.0f;
+    if (jj > 0) l2 += pc - p[f - NF];
+    if (jj < a.m2 - 1) l2 += pc - p[f + NF];
+    if (kk > 0) l3 += pc - p[f - plane];
+    if (kk < a.m3 - 1) l3 += pc - p[f + plane];
+    y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
+    q[f] = y;
+    acc[0] += (double)pc * y;
+  }
+  block_partials<1>(acc, partial, blockIdx.x);
+}
+
+// p = z + beta p (PCG direction update)
+__global__ __launch_bounds__(256) void k_pupdate(long long n, const float* __restrict__ z,
+                                                 float* __restrict__ p, const DevState* st) {
+  if (st->pcg_done) return;
+  const float be = (float)st->beta_cg;
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  for (long long f = lo + threadIdx.x; f < hi; f += blockDim.x) p[f] = fmaf(be, p[f], z[f]);
+}
+
+__global__ __launch_bounds__(256) void k_dot(long long n, const float* __restrict__ x,
+                                             const float* __restrict__ y, double* partial) {
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  double acc[1] = {0.0};
+  for (long long f = lo + threadIdx.x; f < hi; f += blockDim.x) acc[0] += (double)x[f] * y[f];
+  block_partials<1>(acc, partial, blockIdx.x);
+}
+
+// b += lam d with the accepted step length (no-op when the line search failed);
+// partial sums |lam d|^2 and |b_old|^2 for the stopping tests (eq. stopping1).
+__global__ __launch_bounds__(256) void k_gn_step(long long n, float* __restrict__ b,
+                                                 const float* __restrict__ d, double* partial,
+                                                 const DevState* st) {
+  const float lam = (float)st->lam_acc;
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  double acc[2] = {0.0, 0.0};
+  for (long long f = lo + threadIdx.x; f < hi; f += blockDim.x) {
+    const float bo = b[f];
+    acc[1] += (double)bo * bo;
+    if (lam > 0.0f) {
+      const float bn = fmaf(lam, d[f], bo);
+      const float s = bn - bo;
+      acc[0] += (double)s * s;
+      b[f] = bn;
+    }
+  }
+  block_partials<2>(acc, partial, blockIdx.x);
+}
+
+// Count cells with |D1 b| > thr (feasibility of a starting guess).
+__global__ __launch_bounds__(256) void k_count_violations(LineArgs a, const float* __restrict__ b,
+                                                          float thr, double* partial) {
+  const int NF = a.M + 1;
+  const long long n = (long long)a.M * a.L;
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  double acc[1] = {0.0};
+  for (long long c = lo + threadIdx.x; c < hi; c += blockDim.x) {
+    const long long line = c / a.M;
+    const int ci = (int)(c % a.M);
+    const long long f = line * NF + ci;
+    const float g = (b[f + 1] - b[f]) * a.inv_hp;
+    if (!(fabsf(g) <= thr)) acc[0] += 1.0;
+  }
+  block_partials<1>(acc, partial, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_count_nonfinite(long long n, const float* __restrict__ x,
+                                                         double* partial) {
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  double acc[1] = {0.0};
+  for (long long f = lo + threadIdx.x; f < hi; f += blockDim.x)
+    if (!(fabsf(x[f]) < 3.4e38f)) acc[0] += 1.0;
+  block_partials<1>(acc, partial, blockIdx.x);
+}
+
+// ------------------------------------------------------------------------------------
+// Finalisation: deterministic float64 reductions of the partial sums and the scalar
+// logic of PCG, the Armijo test and the ADMM stopping test (eq. admmStop).
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_finalize(FinArgs f, DevState* st) {
+  __shared__ double s[8];
+  __shared__ double s2[8];
+  __shared__ double s3[8];
+  switch (f.kind) {
+    case FIN_EVAL: {
+      reduce_partials<NQ_EVAL>(f.partial, f.nb1, s);
+      if (threadIdx.x == 0) {
+        st->evalD = 0.5 * f.v * s[0];
+        st->evalS1 = s[1];
+        st->evalSx = s[2];
+        st->evalP = s[3];
+        st->eval_infeasible = (int)s[4];
+        st->evalG2 = s[5];
+      }
+    } break;
+    case FIN_PCG_INIT: {
+      reduce_partials<2>(f.partial, f.nb1, s);
+      if (threadIdx.x == 0) {
+        st->rz = s[0];
+        st->rhs2 = s[1];
+        st->pcg_iters = 0;
+        st->pcg_done = !(s[1] > 0.0);
+        st->relres = (s[1] > 0.0) ? 1.0 : 0.0;
+      }
+    } break;
+    case FIN_PCG_ALPHA: {
+      if (st->pcg_done) return;
+      reduce_partials<1>(f.partial, f.nb1, s);
+      if (threadIdx.x == 0) {
+        st->pq = s[0];
+        if (s[0] > 0.0) {
+          st->alpha_cg = st->rz / s[0];
+        } else {
+          st->alpha_cg = 0.0;
+          st->pcg_done = 1;
+        }
+      }
+    } break;
+    case FIN_PCG_UPDATE: {
+      if (st->pcg_done) return;
+      reduce_partials<2>(f.partial, f.nb1, s);
+      if (threadIdx.x == 0) {
+        const double rr = s[0], rzn = s[1];
+        st->rr = rr;
+        st->pcg_iters += 1;
+        st->relres = sqrt(rr / st->rhs2);
+        if (rr <= st->eta2 * st->rhs2 || !(rzn == rzn)) {
+          st->pcg_done = 1;
+        } else {
+          st->beta_cg = rzn / st->rz;
+          st->rz = rzn;
+        }
+      }
+    } break;
+    case FIN_DOT: {
+      reduce_partials<1>(f.partial, f.nb1, s);
+      if (threadIdx.x == 0) st->gTd = s[0];
+    } break;
+    case FIN_LS: {
+      if (st->ls_done) return;
+      reduce_partials<NQ_EVAL>(f.partial, f.nb1, s);
+      if (threadIdx.x == 0) {
+        const double J = 0.5 * f.v * s[0] + f.alpha * 0.5 * f.v * (s[1] + s[2]) +
+                         f.beta * f.v * s[3];
+        const double lam = ldexp(1.0, -f.trial);
+        st->ls_trials = f.trial + 1;
+        if (s[4] == 0.0 && J <= st->J0 + st->c1 * lam * st->gTd) {
+          st->ls_done = 1;
+          st->lam_acc = lam;
+          st->J_acc = J;
+        }
+      }
+    } break;
+    case FIN_STEP: {
+      reduce_partials<2>(f.partial, f.nb1, s);
+      if (threadIdx.x == 0) {
+        st->step2 = s[0];
+        st->bold2 = s[1];
+      }
+    } break;
+    case FIN_ADMM: {
+      if (st->admm_done) return;
+      reduce_partials<1>(f.partial, f.nb1, s);
+      reduce_partials<1>(f.partial2, f.nb2, s2);
+      reduce_partials<4>(f.partial3, f.nb3, s3);
+      if (threadIdx.x == 0) {
+        const double b2 = s[0] + s2[0];
+        const double rho = st->rho;
+        const double rpri = sqrt(s3[0]);
+        const double rdual = rho * st->v * sqrt(s3[1]);
+        const double nb = sqrt(b2), nz = sqrt(s3[2]), nu = sqrt(s3[3]);
+        const double epri = st->sqrt_n * st->eps_abs + st->eps_rel * (nb > nz ? nb : nz);
+        const double edual = st->sqrt_n * st->eps_abs + st->eps_rel * rho * st->v * nu;
+        const int it = st->admm_iter;
+        if (it < f.hist_len) {
+          f.hist[it] = rpri;
+          f.hist[f.hist_len + it] = rdual;
+          f.hist[2 * f.hist_len + it] = epri;
+          f.hist[3 * f.hist_len + it] = edual;
+        }
+        st->admm_iter = it + 1;
+        st->hard_total += st->hard_count;
+        st->hard_count = 0;
+        const bool finite = (rpri == rpri) && (rdual == rdual) && rpri < 1e300 && rdual < 1e300;
+        if (!finite || st->numeric_bad) {
+          st->numeric_bad += 1;
+          st->admm_done = 1;
+        } else if (rpri <= epri && rdual <= edual) {
+          st->admm_done = 1;
+        } else if (st->admm_iter >= st->admm_max) {
+          st->admm_done = 2;   // iteration cap: later launches of this solve are no-ops
+        }
+      }
+    } break;
+    case FIN_LS_INIT: {
+      if (threadIdx.x == 0) {
+        st->J0 = f.value;
+        st->ls_done = 0;
+        st->ls_trials = 0;
+        st->lam_acc = 0.0;
+        st->J_acc = f.value;
+      }
+    } break;
+    case FIN_HARD_RESET: {
+      if (threadIdx.x == 0 && !st->admm_done) {
+        st->hard_total += st->hard_count;
+        st->hard_count = 0;
+      }
+    } break;
+    default:
+      break;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------
+void launch_matvec(hipStream_t s, LineArgs a, const float* p, const float* hdiag,
+                   const float* hoff, float* q, double* partial, const DevState* st) {
+  const long long n = (long long)(a.M + 1) * a.L;
+  hipLaunchKernelGGL(k_matvec, dim3(flat_blocks(n)), dim3(256), 0, s, a, p, hdiag, hoff, q,
+                     partial, st);
+}
+void launch_pupdate(hipStream_t s, long long n, const float* z, float* p, const DevState* st) {
+  hipLaunchKernelGGL(k_pupdate, dim3(flat_blocks(n)), dim3(256), 0, s, n, z, p, st);
+}
+void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial) {
+  hipLaunchKernelGGL(k_dot, dim3(flat_blocks(n)), dim3(256), 0, s, n, x, y, partial);
+}
+void launch_gn_step(hipStream_t s, long long n, float* b, const float* d, double* partial,
+                    const DevState* st) {
+  hipLaunchKernelGGL(k_gn_step, dim3(flat_blocks(n)), dim3(256), 0, s, n, b, d, partial, st);
+}
+void launch_count_violations(hipStream_t s, LineArgs a, const float* b, float thr,
+                             double* partial) {
+  const long long n = (long long)a.M * a.L;
+  hipLaunchKernelGGL(k_count_violations, dim3(flat_blocks(n)), dim3(256), 0, s, a, b, thr,
+                     partial);
+}
+void launch_count_nonfinite(hipStream_t s, long long n, const float* x, double* partial) {
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(flat_blocks(n)), dim3(256), 0, s, n, x, partial);
+}
+void launch_finalize(hipStream_t s, const FinArgs& f, DevState* st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, f, st);
+}
+
+}  // namespace epi

@@ -1,0 +1,262 @@
+"""Python binding of libepi.so (ctypes): argument marshalling only.
+
+Every step of the solvers runs in the HIP kernels of the library; this module turns torch
+tensors into device pointers, option dictionaries into the C structs of ``include/epi.h``
+and report arrays back into Python lists. PyTorch supplies device memory and streams.
+Missing library -> ImportError; a failing call -> EpiError with the library's message.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libepi.so")
+
+EPI_OK, EPI_EINVAL, EPI_ENOMEM, EPI_EINFEASIBLE, EPI_ENUMERIC, EPI_EHIP, EPI_ENOTSUP = range(7)
+STATUS_NAMES = {0: "EPI_OK", 1: "EPI_EINVAL", 2: "EPI_ENOMEM", 3: "EPI_EINFEASIBLE",
+                4: "EPI_ENUMERIC", 5: "EPI_EHIP", 6: "EPI_ENOTSUP"}
+PREC = {"fp32": 0, "mixed": 1}
+PRECOND = {"block": 0, "jacobi": 1, "none": 2}
+
+
+class EpiError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("m", C.c_int32 * 3), ("h", C.c_double * 3),
+                ("alpha", C.c_double), ("beta", C.c_double), ("gamma", C.c_double),
+                ("precision", C.c_int32)]
+
+
+class Terms(C.Structure):
+    _fields_ = [("J", C.c_double), ("D", C.c_double), ("S", C.c_double), ("P", C.c_double),
+                ("feasible", C.c_int32)]
+
+
+class GNOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("pcg_max", C.c_int32), ("precond", C.c_int32),
+                ("ls_max", C.c_int32), ("use_stopping", C.c_int32), ("eta", C.c_double),
+                ("eps_obj", C.c_double), ("eps_iter", C.c_double), ("eps_grad", C.c_double),
+                ("ls_c1", C.c_double), ("rel_grad_tol", C.c_double)]
+
+
+class GNReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32),
+                ("ls_failed", C.c_int32), ("J", C.POINTER(C.c_double)),
+                ("grad_norm", C.POINTER(C.c_double)), ("pcg_relres", C.POINTER(C.c_double)),
+                ("step", C.POINTER(C.c_double)), ("pcg_iters", C.POINTER(C.c_int32))]
+
+
+class ADMMOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("sqp_iters", C.c_int32), ("check_every", C.c_int32),
+                ("rho", C.c_double), ("eps_abs", C.c_double), ("eps_rel", C.c_double)]
+
+
+class ADMMReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32),
+                ("max_active", C.c_int32), ("hard_lines", C.c_int64),
+                ("r_pri", C.POINTER(C.c_double)), ("r_dual", C.POINTER(C.c_double)),
+                ("eps_pri", C.POINTER(C.c_double)), ("eps_dual", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    """Load libepi.so once (ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1607_00531_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, st = C.c_void_p, C.c_int
+        L.epi_abi_version.restype = C.c_int32
+        L.epi_last_error.restype = C.c_char_p
+        L.epi_setup.argtypes = [C.POINTER(Grid), vp, vp, vp, C.POINTER(vp)]
+        L.epi_setup.restype = st
+        L.epi_objective.argtypes = [vp, vp, C.c_int32, C.POINTER(Terms), vp]
+        L.epi_objective.restype = st
+        L.epi_smooth_solve.argtypes = [vp, vp, C.c_double, vp]
+        L.epi_smooth_solve.restype = st
+        L.epi_solve_gnpcg.argtypes = [vp, vp, C.POINTER(GNOpts), C.POINTER(GNReport)]
+        L.epi_solve_gnpcg.restype = st
+        L.epi_solve_admm.argtypes = [vp, vp, vp, vp, C.POINTER(ADMMOpts), C.POINTER(ADMMReport)]
+        L.epi_solve_admm.restype = st
+        L.epi_destroy.argtypes = [vp]
+        L.epi_destroy.restype = None
+        L.epi_gn_default_opts.argtypes = [C.POINTER(GNOpts)]
+        L.epi_admm_default_opts.argtypes = [C.POINTER(ADMMOpts)]
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != EPI_OK:
+        raise EpiError(status, lib().epi_last_error().decode(errors="replace"))
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError("expected a float32 CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous (canonical layout)")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def to_canonical(t, pe_axis: int):
+    """Caller-order tensor (2D or 3D, cells or PE faces) -> canonical contiguous layout
+    (m3, m2, M[+1]): PE axis last (contiguous), the other axes in order, m3 = 1 in 2D."""
+    nd = t.dim()
+    rest = [a for a in range(nd) if a != pe_axis]
+    if nd == 2:
+        return t.permute(rest[0], pe_axis).unsqueeze(0).contiguous()
+    if nd == 3:
+        return t.permute(rest[1], rest[0], pe_axis).contiguous()
+    raise ValueError("2D or 3D tensors only")
+
+
+def from_canonical(t, ndim: int, pe_axis: int):
+    rest = [a for a in range(ndim) if a != pe_axis]
+    if ndim == 2:
+        order = [rest[0], pe_axis]
+        inv = [order.index(a) for a in range(2)]
+        return t[0].permute(*inv).contiguous()
+    order = [rest[1], rest[0], pe_axis]
+    inv = [order.index(a) for a in range(3)]
+    return t.permute(*inv).contiguous()
+
+
+def gn_default_opts() -> dict:
+    o = GNOpts()
+    lib().epi_gn_default_opts(C.byref(o))
+    d = {k: getattr(o, k) for k, _ in GNOpts._fields_}
+    d["precond"] = {v: k for k, v in PRECOND.items()}[d["precond"]]
+    return d
+
+
+def admm_default_opts() -> dict:
+    o = ADMMOpts()
+    lib().epi_admm_default_opts(C.byref(o))
+    return {k: getattr(o, k) for k, _ in ADMMOpts._fields_}
+
+
+class Problem:
+    """A problem handle (epi_setup). Ip, Im: float32 CUDA tensors of shape (m3, m2, M) in
+    canonical layout; h = (h_p, h2, h3) with h3 = 1 in 2D. The images are borrowed: they
+    are kept referenced here for the lifetime of the handle."""
+
+    def __init__(self, Ip, Im, h, alpha: float, beta: float = 10.0, gamma: float = 1e-3,
+                 precision: str = "mixed", ndim: Optional[int] = None, stream=None):
+        if Ip.dim() != 3 or Ip.shape != Im.shape:
+            raise ValueError("Ip and Im must have the same canonical shape (m3, m2, M)")
+        m3, m2, M = (int(s) for s in Ip.shape)
+        self.shape_cells = (m3, m2, M)
+        self.shape_faces = (m3, m2, M + 1)
+        self.ndim = ndim if ndim is not None else (2 if m3 == 1 else 3)
+        self.h = tuple(float(x) for x in h)
+        self.alpha, self.beta, self.gamma = float(alpha), float(beta), float(gamma)
+        self.precision = precision
+        self._Ip, self._Im = Ip, Im
+        self._stream = stream
+        g = Grid()
+        g.ndim = self.ndim
+        g.m[0], g.m[1], g.m[2] = M, m2, m3
+        for a in range(3):
+            g.h[a] = self.h[a]
+        g.alpha, g.beta, g.gamma = self.alpha, self.beta, self.gamma
+        g.precision = PREC[precision]
+        self._h = C.c_void_p()
+        _check(lib().epi_setup(C.byref(g), _ptr(Ip), _ptr(Im), _stream_handle(stream),
+                               C.byref(self._h)))
+
+    @property
+    def n(self) -> int:
+        m3, m2, M = self.shape_cells
+        return (M + 1) * m2 * m3
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().epi_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _faces(self, t):
+        if tuple(t.shape) != self.shape_faces:
+            raise ValueError(f"expected face array of shape {self.shape_faces}, got {tuple(t.shape)}")
+        return _ptr(t)
+
+    def objective(self, b, with_penalty: bool = True, grad=None) -> dict:
+        t = Terms()
+        gp = self._faces(grad) if grad is not None else None
+        _check(lib().epi_objective(self._h, self._faces(b), 1 if with_penalty else 0,
+                                   C.byref(t), gp))
+        return dict(J=t.J, D=t.D, S=t.S, P=t.P, feasible=bool(t.feasible))
+
+    def smooth_solve(self, w, rho: float, out=None):
+        import torch
+        z = torch.empty_like(w) if out is None else out
+        _check(lib().epi_smooth_solve(self._h, self._faces(w), float(rho), self._faces(z)))
+        return z
+
+    def solve_gnpcg(self, b, **kw) -> dict:
+        o = GNOpts()
+        lib().epi_gn_default_opts(C.byref(o))
+        for k, v in kw.items():
+            if k == "precond":
+                v = PRECOND[v] if isinstance(v, str) else int(v)
+            setattr(o, k, v)
+        n1 = max(o.max_iter, 0) + 1
+        arrs = {k: (C.c_double * n1)() for k in ("J", "grad_norm", "pcg_relres", "step")}
+        its = (C.c_int32 * n1)()
+        rep = GNReport()
+        for k, a in arrs.items():
+            setattr(rep, k, C.cast(a, C.POINTER(C.c_double)))
+        rep.pcg_iters = C.cast(its, C.POINTER(C.c_int32))
+        _check(lib().epi_solve_gnpcg(self._h, self._faces(b), C.byref(o), C.byref(rep)))
+        k = rep.iters
+        return dict(iters=k, converged=bool(rep.converged), ls_failed=bool(rep.ls_failed),
+                    J=list(arrs["J"][:k + 1]), grad_norm=list(arrs["grad_norm"][:k + 1]),
+                    pcg_relres=list(arrs["pcg_relres"][:k]), step=list(arrs["step"][:k]),
+                    pcg_iters=list(its[:k]))
+
+    def solve_admm(self, b, z, u, **kw) -> dict:
+        o = ADMMOpts()
+        lib().epi_admm_default_opts(C.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        n1 = max(o.max_iter, 1)
+        arrs = {k: (C.c_double * n1)() for k in ("r_pri", "r_dual", "eps_pri", "eps_dual")}
+        rep = ADMMReport()
+        for k, a in arrs.items():
+            setattr(rep, k, C.cast(a, C.POINTER(C.c_double)))
+        _check(lib().epi_solve_admm(self._h, self._faces(b), self._faces(z), self._faces(u),
+                                    C.byref(o), C.byref(rep)))
+        k = rep.iters
+        out = dict(iters=k, converged=bool(rep.converged), max_active=rep.max_active,
+                   hard_lines=int(rep.hard_lines))
+        for key, a in arrs.items():
+            out[key] = list(a[:k])
+        return out

@@ -1,0 +1,291 @@
+"""GPU (HIP, gfx950) path against the FP64 oracle, through the C ABI (python binding)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import generate, config_volume, CONFIGS
+from tests.gpu_common import T, N, J_REL, FIELD_VOX, hist_ok, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(v, alpha, prec="mixed", beta=10.0):
+    from paper_1607_00531_amd import Problem
+    return Problem(T(v.Ip), T(v.Im), v.h, alpha, beta=beta, precision=prec)
+
+
+def _smooth_field(P, seed, gmax):
+    r = np.random.default_rng(seed)
+    b = np.cumsum(r.normal(size=(P.L, P.M + 1)), axis=1)
+    b -= b.mean(axis=1, keepdims=True)
+    g = np.diff(b, axis=1) / P.hp
+    return b * (gmax / np.abs(g).max())
+
+
+# shapes (caller order, PE axis) chosen to cover 1..8 faces per lane, ragged tiles, m2 = 1
+SHAPES = [((32, 40), 1), ((16, 20, 12), 0), ((64, 64), 1), ((240, 8, 6), 0),
+          ((20, 70, 9), 1), ((3, 130, 5), 1), ((300, 3, 2), 0), ((350, 2, 2), 0),
+          ((420, 2, 3), 0), ((511, 4, 3), 0), ((2, 9, 1), 1)]
+
+
+@pytest.mark.parametrize("shape,pe", SHAPES)
+def test_objective_and_gradient(shape, pe):
+    v = generate(2, shape, pe)
+    P = O.make_problem(v.Ip, v.Im, v.h, 0.7)
+    with _problem(v, 0.7) as pr:
+        for bb in (np.zeros((P.L, P.M + 1)), v.b_true.reshape(P.L, -1), _smooth_field(P, 3, 0.6)):
+            for pen in (True, False):
+                g = T(np.zeros(pr.shape_faces))
+                t = pr.objective(T(bb.reshape(pr.shape_faces)), pen, grad=g)
+                o = O.objective(P, bb, pen)
+                for key in ("J", "D", "S", "P"):
+                    ref = o[key]
+                    assert abs(t[key] - ref) <= J_REL * max(abs(o["J"]), 1e-300), (key, t, o)
+                assert t["feasible"] == o["feasible"]
+                go = O.gradient(P, bb, pen).reshape(-1)
+                err = np.abs(N(g).reshape(-1) - go).max()
+                assert err <= 2e-4 * np.abs(go).max(), err / np.abs(go).max()
+
+
+def test_objective_infeasible_penalty_is_inf():
+    v = generate(2, (24, 18), 1)
+    P = O.make_problem(v.Ip, v.Im, v.h, 0.7)
+    b = np.zeros((P.L, P.M + 1))
+    b[:, 5:] += 1.5 * P.hp                      # D1 b = 1.5 on cell 4 of every line
+    with _problem(v, 0.7) as pr:
+        t = pr.objective(T(b.reshape(pr.shape_faces)), True)
+        assert not t["feasible"] and math.isinf(t["J"]) and math.isinf(t["P"])
+        t2 = pr.objective(T(b.reshape(pr.shape_faces)), False)
+        assert abs(t2["J"] - O.objective(P, b, False)["J"]) <= J_REL * abs(t2["J"])
+
+
+SMOOTH_SHAPES = [((16, 20, 12), 0), ((64, 64), 1), ((20, 70, 9), 1), ((9, 256, 3), 1),
+                 ((5, 33, 200), 0), ((7, 1, 17), 0), ((12, 5, 256), 1)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("mixed", 5e-5)])
+@pytest.mark.parametrize("shape,pe", SMOOTH_SHAPES)
+def test_smooth_solve(shape, pe, prec, tol):
+    v = generate(3, shape, pe, n_blobs=2, n_bumps=1)
+    P = O.make_problem(v.Ip, v.Im, v.h, 3.0)
+    w = np.random.default_rng(4).normal(size=P.n)
+    with _problem(v, 3.0, prec) as pr:
+        for rho in (1.0, 1e3):
+            z = pr.smooth_solve(T(w.reshape(pr.shape_faces)), rho)
+            zo = O.zstep(P, w, rho).reshape(-1)
+            err = np.abs(N(z).reshape(-1) - zo).max() / np.abs(zo).max()
+            assert err <= tol, err
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("shape,pe,alpha", [((64, 64), 1, 50.0), ((240, 8, 6), 0, 0.5),
+                                            ((20, 70, 9), 1, 0.5), ((16, 20, 12), 0, 0.5)])
+def test_admm_one_iteration_from_the_same_state(shape, pe, alpha, prec):
+    v = generate(1, shape, pe)
+    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
+    rho = 1e3
+    b0, z0, u0 = np.zeros((P.L, P.M + 1)), np.zeros((P.L, P.M + 1)), np.zeros((P.L, P.M + 1))
+    b0, z0, u0, _ = O.solve_admm(P, rho=rho, max_iter=3, eps_abs=0, eps_rel=0)
+    b0, z0, u0 = (P.lines(x) for x in (b0, z0, u0))
+    bn, _, _ = O.bstep(P, b0, z0, u0, rho)
+    zn = O.zstep(P, bn + u0, rho)
+    un = u0 + bn - zn
+    with _problem(v, alpha, prec) as pr:
+        sh = pr.shape_faces
+        b, z, u = T(b0.reshape(sh)), T(z0.reshape(sh)), T(u0.reshape(sh))
+        rep = pr.solve_admm(b, z, u, rho=rho, max_iter=1, eps_abs=0.0, eps_rel=0.0)
+        assert rep["iters"] == 1
+        for gpu, cpu in ((b, bn), (z, zn), (u, un)):
+            err = np.abs(N(gpu).reshape(P.L, -1) - cpu).max() / P.hp
+            assert err <= FIELD_VOX, err
+
+
+def test_admm_active_set_lines():
+    """A state that drives many lines onto the bound |D1 b| = 1: the active-set path."""
+    r = np.random.default_rng(17)
+    M, m2, m3 = 12, 6, 4
+    Ip = 3.0 * r.uniform(0.2, 1.0, size=(m3, m2, M))
+    Im = 3.0 * r.uniform(0.2, 1.0, size=(m3, m2, M))
+    h = (1 / M, 1 / m2, 1 / m3)
+    P = O.make_problem(Ip, Im, h, 0.02)
+    b = _smooth_field(P, 9, 0.7)
+    z = b + 0.3 * P.hp * r.normal(size=b.shape)
+    u = 0.1 * P.hp * r.normal(size=b.shape)
+    rho = 50.0
+    bn, nact, _ = O.bstep(P, b, z, u, rho)
+    assert nact.max() > 0
+    zn = O.zstep(P, bn + u, rho)
+    un = u + bn - zn
+    from paper_1607_00531_amd import Problem
+    for prec in ("fp32", "mixed"):
+        with Problem(T(Ip), T(Im), h, 0.02, precision=prec) as pr:
+            sh = pr.shape_faces
+            bg, zg, ug = T(b.reshape(sh)), T(z.reshape(sh)), T(u.reshape(sh))
+            rep = pr.solve_admm(bg, zg, ug, rho=rho, max_iter=1, eps_abs=0.0, eps_rel=0.0)
+            assert rep["hard_lines"] > 0 and rep["max_active"] == int(nact.max())
+            for gpu, cpu in ((bg, bn), (zg, zn), (ug, un)):
+                err = np.abs(N(gpu).reshape(P.L, -1) - cpu).max() / P.hp
+                assert err <= FIELD_VOX, err
+            gnew = np.diff(N(bg).reshape(P.L, -1), axis=1) / P.hp
+            assert np.abs(gnew).max() <= 1.0 + 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("shape,pe,alpha,iters", [((64, 64), 1, 50.0, 20),
+                                                  ((20, 70, 9), 1, 0.5, 20),
+                                                  ((40, 36, 24), 2, 5.0, 15)])
+def test_admm_trajectory(shape, pe, alpha, iters, prec):
+    v = generate(0, shape, pe)
+    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
+    bo, zo, uo, ro = O.solve_admm(P, rho=1e3, max_iter=iters, eps_abs=0.0, eps_rel=0.0)
+    with _problem(v, alpha, prec) as pr:
+        b = T(np.zeros(pr.shape_faces))
+        z, u = b.clone(), b.clone()
+        rep = pr.solve_admm(b, z, u, rho=1e3, max_iter=iters, eps_abs=0.0, eps_rel=0.0)
+        assert rep["iters"] == iters and not rep["converged"]
+        for gpu, cpu in ((b, bo), (z, zo), (u, uo)):
+            err = np.abs(N(gpu) - cpu).max() / P.hp
+            assert err <= FIELD_VOX, err
+        scale = max(np.linalg.norm(bo), np.linalg.norm(zo))
+        for key, ref in (("r_pri", ro.r_pri), ("r_dual", ro.r_dual)):
+            ok, msg = hist_ok(rep[key], ref, scale if key == "r_pri" else scale * 1e3 * P.v, prec)
+            assert ok, (key, msg)
+        for key, ref in (("eps_pri", ro.eps_pri), ("eps_dual", ro.eps_dual)):
+            ok, msg = hist_ok(rep[key], ref, 0.0, prec)
+            assert ok, (key, msg)
+
+
+def test_admm_stopping_rule_matches_oracle():
+    v = config_volume("c1_2d_64", 0)
+    P = O.make_problem(v.Ip, v.Im, v.h, 50.0)
+    bo, zo, uo, ro = O.solve_admm(P, rho=1e3, max_iter=300, eps_abs=0.0, eps_rel=1e-3)
+    assert ro.converged
+    with _problem(v, 50.0, "fp32") as pr:
+        b = T(np.zeros(pr.shape_faces))
+        z, u = b.clone(), b.clone()
+        rep = pr.solve_admm(b, z, u, rho=1e3, max_iter=300, eps_abs=0.0, eps_rel=1e-3,
+                            check_every=16)
+        assert rep["converged"]
+        assert abs(rep["iters"] - ro.iters) <= 2, (rep["iters"], ro.iters)
+        assert np.abs(N(b) - bo).max() / P.hp <= FIELD_VOX
+
+
+def test_admm_results_independent_of_polling_and_resumable():
+    v = generate(5, (48, 40), 1)
+    with _problem(v, 5.0, "mixed") as pr:
+        outs = []
+        for ce in (1, 7):
+            b = T(np.zeros(pr.shape_faces))
+            z, u = b.clone(), b.clone()
+            pr.solve_admm(b, z, u, rho=1e3, max_iter=12, eps_abs=0.0, eps_rel=0.0, check_every=ce)
+            outs.append((N(b), N(z), N(u)))
+        b = T(np.zeros(pr.shape_faces))
+        z, u = b.clone(), b.clone()
+        pr.solve_admm(b, z, u, rho=1e3, max_iter=5, eps_abs=0.0, eps_rel=0.0)
+        pr.solve_admm(b, z, u, rho=1e3, max_iter=7, eps_abs=0.0, eps_rel=0.0)
+        outs.append((N(b), N(z), N(u)))
+    for o in outs[1:]:
+        for a, c in zip(outs[0], o):
+            np.testing.assert_array_equal(a, c)
+
+
+@pytest.mark.parametrize("precond", ["block", "jacobi", "none"])
+def test_gnpcg_trajectory_config_c1(precond):
+    v = config_volume("c1_2d_64", 0)
+    alpha = CONFIGS["c1_2d_64"]["alpha"]
+    its = CONFIGS["c1_2d_64"]["iters"]
+    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
+    bo, ro = O.solve_gnpcg(P, max_iter=its, use_stopping=False, precond=precond)
+    with _problem(v, alpha, "fp32") as pr:
+        b = T(np.zeros(pr.shape_faces))
+        rep = pr.solve_gnpcg(b, max_iter=its, use_stopping=0, precond=precond)
+        assert rep["iters"] == ro.iters
+        np.testing.assert_allclose(rep["J"], ro.J, rtol=J_REL)
+        assert np.abs(N(b) - bo).max() / P.hp <= FIELD_VOX
+        assert sum(abs(a - c) for a, c in zip(rep["pcg_iters"], ro.pcg_iters)) <= 2
+
+
+@pytest.mark.parametrize("shape,pe,alpha", [((240, 8, 6), 0, 0.5), ((20, 70, 9), 1, 0.05),
+                                            ((16, 20, 12), 0, 0.5)])
+def test_gnpcg_trajectory_data_dominated(shape, pe, alpha):
+    v = generate(1, shape, pe)
+    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
+    bo, ro = O.solve_gnpcg(P, max_iter=6, use_stopping=False)
+    with _problem(v, alpha, "mixed") as pr:
+        b = T(np.zeros(pr.shape_faces))
+        rep = pr.solve_gnpcg(b, max_iter=6, use_stopping=0)
+        # Along a trajectory the iterates themselves differ: the line systems have condition
+        # numbers ~1e4, so float32 rounding of G and c alone moves each GN direction by
+        # ~1e-5 relative; the objective is compared on the scale of the problem, J(b0).
+        np.testing.assert_allclose(rep["J"], ro.J, rtol=0, atol=J_REL * ro.J[0])
+        assert rep["pcg_iters"] == ro.pcg_iters
+        assert np.abs(N(b) - bo).max() / P.hp <= FIELD_VOX
+
+
+def test_gnpcg_stopping_rule():
+    v = generate(1, (40, 32), 1)
+    P = O.make_problem(v.Ip, v.Im, v.h, 0.5)
+    bo, ro = O.solve_gnpcg(P, max_iter=30)
+    with _problem(v, 0.5, "fp32") as pr:
+        b = T(np.zeros(pr.shape_faces))
+        rep = pr.solve_gnpcg(b, max_iter=30)
+        assert rep["converged"] == ro.converged and rep["iters"] == ro.iters
+
+
+def test_errors_are_reported():
+    from paper_1607_00531_amd import EpiError, EPI_EINFEASIBLE, EPI_ENUMERIC, EPI_EINVAL
+    v = generate(2, (24, 18), 1)
+    P = O.make_problem(v.Ip, v.Im, v.h, 0.7)
+    bad = np.zeros((P.L, P.M + 1))
+    bad[:, 5:] += 1.5 * P.hp
+    with _problem(v, 0.7) as pr:
+        sh = pr.shape_faces
+        with pytest.raises(EpiError) as e:
+            pr.solve_gnpcg(T(bad.reshape(sh)))
+        assert e.value.status == EPI_EINFEASIBLE
+        with pytest.raises(EpiError) as e:
+            pr.solve_admm(T(bad.reshape(sh)), T(bad.reshape(sh)), T(np.zeros(sh)))
+        assert e.value.status == EPI_EINFEASIBLE
+        with pytest.raises(EpiError) as e:
+            pr.solve_admm(T(np.zeros(sh)), T(np.zeros(sh)), T(np.zeros(sh)), rho=-1.0)
+        assert e.value.status == EPI_EINVAL
+    Ip = v.Ip.copy()
+    Ip[0, 3, 4] = np.nan
+    from paper_1607_00531_amd import Problem
+    with pytest.raises(EpiError) as e:
+        Problem(T(Ip), T(v.Im), v.h, 0.7)
+    assert e.value.status == EPI_ENUMERIC
+    with pytest.raises(EpiError) as e:
+        Problem(T(np.zeros((1, 4, 600))), T(np.zeros((1, 4, 600))), (1.0, 1.0, 1.0), 1.0)
+    assert e.value.status == EPI_EINVAL
+
+
+def test_degenerate_shifted_out_field():
+    """Constant field of M voxels: both images leave the domain, D = S = 0; the ADMM state
+    with z = b, u = 0 has zero gradient apart from the proximal term and stays put."""
+    v = generate(4, (30, 20), 1)
+    P = O.make_problem(v.Ip, v.Im, v.h, 1.0)
+    b = np.full((P.L, P.M + 1), P.M * P.hp)
+    with _problem(v, 1.0) as pr:
+        t = pr.objective(T(b.reshape(pr.shape_faces)), True)
+        assert t["D"] == 0.0 and abs(t["S"]) < 1e-12
+        bg, zg, ug = T(b.reshape(pr.shape_faces)), T(b.reshape(pr.shape_faces)), T(np.zeros(pr.shape_faces))
+        pr.solve_admm(bg, zg, ug, rho=10.0, max_iter=3, eps_abs=0.0, eps_rel=0.0)
+        assert np.abs(N(bg).reshape(P.L, -1) - b).max() / P.hp <= FIELD_VOX
+
+
+def test_deterministic():
+    v = generate(6, (24, 30, 20), 0)
+    outs = []
+    for _ in range(2):
+        with _problem(v, 2.0, "mixed") as pr:
+            b = T(np.zeros(pr.shape_faces))
+            z, u = b.clone(), b.clone()
+            r1 = pr.solve_admm(b, z, u, rho=1e3, max_iter=6, eps_abs=0.0, eps_rel=0.0)
+            bg = T(np.zeros(pr.shape_faces))
+            r2 = pr.solve_gnpcg(bg, max_iter=3, use_stopping=0)
+            outs.append((N(b), N(z), N(bg), r1["r_pri"], r2["J"]))
+    for a, c in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(np.asarray(a), np.asarray(c))
