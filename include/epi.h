@@ -124,6 +124,24 @@ typedef struct {
   double *r_pri, *r_dual, *eps_pri, *eps_dual;
 } epi_admm_report;
 
+/* Kernel families of one ADMM iteration, for epi_profile_admm. */
+enum {
+  EPI_K_BSTEP = 0,       /* b-step, unconstrained fast path (all lines)            */
+  EPI_K_BSTEP_HARD = 1,  /* b-step, active-set path (lines that need it)            */
+  EPI_K_DCT_AXIS3 = 2,   /* z-step DCT along the third axis (forward)              */
+  EPI_K_DCT_AXIS2 = 3,   /* z-step DCT along the second axis, scaled, inverse       */
+  EPI_K_DCT_LAST = 4,    /* last z-step pass with the u-step epilogue              */
+  EPI_K_FINALIZE = 5,    /* float64 residual norms and stopping test               */
+  EPI_K_COUNT = 6
+};
+
+/* Per-kernel-family device time of a profiled ADMM solve (milliseconds, HIP events on
+ * the library's stream around every launch) and the number of launches. */
+typedef struct {
+  double ms[8];
+  int64_t launches[8];
+} epi_kernel_profile;
+
 typedef struct epi_problem epi_problem;
 
 /* Library ABI version (EPI_ABI_VERSION). */
@@ -167,6 +185,14 @@ epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts* opts,
  * convergence are no-ops, so the state on exit is the state at the stopping iteration. */
 epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
                           const epi_admm_opts* opts, epi_admm_report* rep);
+
+/* The same solve as epi_solve_admm (same kernels in the same order, same results),
+ * launched one kernel at a time without the captured graph, with a pair of HIP events
+ * around every kernel on the library's stream. prof receives the device time per kernel
+ * family. For measurement tools; slower than epi_solve_admm by the launch overhead. */
+epi_status epi_profile_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
+                            const epi_admm_opts* opts, epi_admm_report* rep,
+                            epi_kernel_profile* prof);
 
 /* Release the handle and its workspace (NULL is a no-op). */
 void epi_destroy(epi_problem* p);

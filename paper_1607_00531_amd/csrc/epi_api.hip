@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -87,7 +88,43 @@ struct epi_problem {
   hipGraph_t graph = nullptr;
   int g_chunk = 0, g_sqp = 0;
   float *g_b = nullptr, *g_z = nullptr, *g_u = nullptr;
+  // per-kernel event timing (epi_profile_admm)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  std::vector<int> prof_kind;
+  int prof_used = 0;
+  double prof_ms[8] = {0};
+  long long prof_cnt[8] = {0};
 };
+
+static void prof_begin(epi_problem* p, int kind) {
+  if (!p->prof_on) return;
+  const size_t need = 2 * (size_t)(p->prof_used + 1);
+  while (p->prof_ev.size() < need) {
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    p->prof_ev.push_back(e);
+  }
+  if (p->prof_kind.size() < (size_t)(p->prof_used + 1)) p->prof_kind.resize(p->prof_used + 1);
+  p->prof_kind[p->prof_used] = kind;
+  (void)hipEventRecord(p->prof_ev[2 * p->prof_used], p->exec);
+}
+static void prof_end(epi_problem* p) {
+  if (!p->prof_on) return;
+  (void)hipEventRecord(p->prof_ev[2 * p->prof_used + 1], p->exec);
+  p->prof_used += 1;
+}
+// after a stream synchronisation: fold the recorded pairs into the totals
+static void prof_collect(epi_problem* p) {
+  for (int i = 0; i < p->prof_used; ++i) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, p->prof_ev[2 * i], p->prof_ev[2 * i + 1]) == hipSuccess) {
+      p->prof_ms[p->prof_kind[i]] += ms;
+      p->prof_cnt[p->prof_kind[i]] += 1;
+    }
+  }
+  p->prof_used = 0;
+}
 
 static void enter(epi_problem* p) {
   (void)hipEventRecord(p->ev_in, p->user);
@@ -247,6 +284,7 @@ EPI_API void epi_destroy(epi_problem* p) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (p->st_h) (void)hipHostFree(p->st_h);
+  for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
   if (p->ev_out) (void)hipEventDestroy(p->ev_out);
   if (p->exec) (void)hipStreamDestroy(p->exec);
@@ -321,14 +359,14 @@ static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float*
   float** bufs[] = {&p->w, &p->t1, &p->t2, &p->g, &p->hd, &p->ho, &p->x, &p->r, &p->zz, &p->p, &p->q};
   for (float** b : bufs) HIPCHK(hipMalloc(b, nb));
   const int lb = line_blocks(a);
-  p->hard_blocks = p->L < 1024 ? p->L : 1024;
+  p->hard_blocks = p->L < 128 ? p->L : 128;
   size_t cap = (size_t)lb * NQ_EVAL;
   cap = std::max(cap, (size_t)2048 * 2);
   cap = std::max(cap, (size_t)std::max(dct_tiles_axis2(p), dct_tiles_axis3(p)) * 4);
   p->partial_cap = cap;
   HIPCHK(hipMalloc(&p->partial, cap * sizeof(double)));
   HIPCHK(hipMalloc(&p->partial_b, ((size_t)lb + p->hard_blocks) * sizeof(double)));
-  HIPCHK(hipMalloc(&p->partial_e, (size_t)std::max(dct_tiles_axis2(p), dct_tiles_axis3(p)) * 4 * sizeof(double)));
+  HIPCHK(hipMalloc(&p->partial_e, (size_t)std::max(dct_tiles_axis2(p), dct_tiles_axis3(p)) * NQ_ADMM_E * sizeof(double)));
   HIPCHK(hipMalloc(&p->st, sizeof(DevState)));
   HIPCHK(hipHostMalloc((void**)&p->st_h, sizeof(DevState), hipHostMallocDefault));
   memset(p->st_h, 0, sizeof(DevState));
@@ -465,17 +503,23 @@ static epi_status launch_zstep(epi_problem* p, const float* w, float* z, int adm
       g2.u = u;
       g2.partial = p->partial_e;
     }
+    prof_begin(p, EPI_K_DCT_LAST);
     launch_dct_axis2_fused(p->exec, prec, g2);
+    prof_end(p);
     CHKLAUNCH();
     return EPI_OK;
   }
   GemmArgs g1 = gemm_axis3(p, w, p->t1, p->A3f);
   g1.done = done;
+  prof_begin(p, EPI_K_DCT_AXIS3);
   launch_dct_axis3(p->exec, prec, g1);
+  prof_end(p);
   CHKLAUNCH();
   GemmArgs g2 = gemm_axis2(p, p->t1, p->t2);
   g2.done = done;
+  prof_begin(p, EPI_K_DCT_AXIS2);
   launch_dct_axis2_fused(p->exec, prec, g2);
+  prof_end(p);
   CHKLAUNCH();
   GemmArgs g3 = gemm_axis3(p, p->t2, z, p->A3i);
   g3.done = done;
@@ -486,7 +530,9 @@ static epi_status launch_zstep(epi_problem* p, const float* w, float* z, int adm
     g3.u = u;
     g3.partial = p->partial_e;
   }
+  prof_begin(p, EPI_K_DCT_LAST);
   launch_dct_axis3(p->exec, prec, g3);
+  prof_end(p);
   CHKLAUNCH();
   return EPI_OK;
 }
@@ -520,23 +566,21 @@ static epi_status admm_iteration(epi_problem* p, float* b, float* z, float* u, i
       f.kind = FIN_HARD_RESET;
       launch_finalize(p->exec, f, p->st);
     }
-    launch_admm_bstep(p->exec, p->P, p->la, b, z, u, p->w, p->hard_list, p->partial_b, p->st,
-                      p->hard_blocks);
+    launch_admm_bstep(p->exec, p->P, p->la, b, z, u, p->w, p->hard_list, p->st, p->hard_blocks,
+                      [&](int k) { prof_begin(p, k); }, [&]() { prof_end(p); });
     CHKLAUNCH();
   }
   epi_status st = launch_zstep(p, p->w, z, 1, b, u);
   if (st != EPI_OK) return st;
   FinArgs f{};
   f.kind = FIN_ADMM;
-  f.partial = p->partial_b;
-  f.nb1 = lb;
-  f.partial2 = p->partial_b + lb;
-  f.nb2 = p->hard_blocks;
-  f.partial3 = p->partial_e;
-  f.nb3 = zstep_epi_blocks(p);
+  f.partial = p->partial_e;
+  f.nb1 = zstep_epi_blocks(p);
   f.hist = p->hist;
   f.hist_len = p->hist_cap;
+  prof_begin(p, EPI_K_FINALIZE);
   launch_finalize(p->exec, f, p->st);
+  prof_end(p);
   CHKLAUNCH();
   return EPI_OK;
 }
@@ -556,8 +600,8 @@ static epi_status count_violations(epi_problem* p, const float* b, float thr, do
   return EPI_OK;
 }
 
-EPI_API epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
-                                     const epi_admm_opts* opts, epi_admm_report* rep) {
+static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float* d_u,
+                                  const epi_admm_opts* opts, epi_admm_report* rep) {
   if (!p || !d_b || !d_z || !d_u || !opts) return fail(EPI_EINVAL, "null argument");
   if (!(opts->rho > 0.0)) return fail(EPI_EINVAL, "rho must be > 0");
   if (opts->max_iter < 0 || opts->sqp_iters < 1 || opts->check_every < 1)
@@ -590,7 +634,7 @@ EPI_API epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float*
   HIPCHK(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->exec));
 
   const int chunk = opts->check_every;
-  const bool use_graph = true;
+  const bool use_graph = !p->prof_on;
   if (use_graph && (p->g_chunk != chunk || p->g_sqp != opts->sqp_iters || p->g_b != d_b ||
                     p->g_z != d_z || p->g_u != d_u)) {
     free_graph(p);
@@ -615,10 +659,18 @@ EPI_API epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float*
   int done = opts->max_iter == 0;
   int launched = 0;
   while (!done) {
-    HIPCHK(hipGraphLaunch(p->gexec, p->exec));
+    if (use_graph) {
+      HIPCHK(hipGraphLaunch(p->gexec, p->exec));
+    } else {
+      for (int i = 0; i < chunk; ++i) {
+        s = admm_iteration(p, d_b, d_z, d_u, opts->sqp_iters);
+        if (s != EPI_OK) return s;
+      }
+    }
     launched += chunk;
     HIPCHK(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
     HIPCHK(hipStreamSynchronize(p->exec));
+    prof_collect(p);
     done = h->admm_done != 0 || launched >= opts->max_iter;
   }
   HIPCHK(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
@@ -639,6 +691,32 @@ EPI_API epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float*
   leave(p);
   if (h->numeric_bad) return fail(EPI_ENUMERIC, "non-finite value during ADMM");
   return EPI_OK;
+}
+
+EPI_API epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
+                                  const epi_admm_opts* opts, epi_admm_report* rep) {
+  if (!p) return fail(EPI_EINVAL, "null argument");
+  p->prof_on = false;
+  return solve_admm_impl(p, d_b, d_z, d_u, opts, rep);
+}
+
+EPI_API epi_status epi_profile_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
+                                    const epi_admm_opts* opts, epi_admm_report* rep,
+                                    epi_kernel_profile* prof) {
+  if (!p || !prof) return fail(EPI_EINVAL, "null argument");
+  p->prof_on = true;
+  p->prof_used = 0;
+  for (int k = 0; k < 8; ++k) {
+    p->prof_ms[k] = 0.0;
+    p->prof_cnt[k] = 0;
+  }
+  epi_status s = solve_admm_impl(p, d_b, d_z, d_u, opts, rep);
+  p->prof_on = false;
+  for (int k = 0; k < 8; ++k) {
+    prof->ms[k] = p->prof_ms[k];
+    prof->launches[k] = p->prof_cnt[k];
+  }
+  return s;
 }
 
 // ------------------------------------------------------------------------------------

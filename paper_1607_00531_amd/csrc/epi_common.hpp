@@ -47,8 +47,7 @@ struct DevState {
 enum : int {
   NQ_EVAL = 6,    // sum r^2, sum g^2, sum cross diffs^2, sum phi, infeasible count, |grad|^2
   NQ_PCG = 2,     // two dot products
-  NQ_ADMM_B = 1,  // |b_new|^2
-  NQ_ADMM_E = 4   // |b-z|^2, |z-z_old|^2, |z|^2, |u|^2
+  NQ_ADMM_E = 5   // |b-z|^2, |z-z_old|^2, |z|^2, |u|^2, |b|^2
 };
 
 // Arguments of the DCT products of the z-step.

@@ -68,9 +68,16 @@ __device__ __forceinline__ void reduce_partials(const double* partial, int nb, d
   const int t = threadIdx.x;
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    double s = 0.0;
-    for (int b = t; b < nb; b += blockDim.x) s += partial[(size_t)b * NQ + q];
-    red[q][t] = s;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = t;
+    for (; b + 768 < nb; b += 1024) {
+      s0 += partial[(size_t)b * NQ + q];
+      s1 += partial[(size_t)(b + 256) * NQ + q];
+      s2 += partial[(size_t)(b + 512) * NQ + q];
+      s3 += partial[(size_t)(b + 768) * NQ + q];
+    }
+    for (; b < nb; b += 256) s0 += partial[(size_t)b * NQ + q];
+    red[q][t] = (s0 + s1) + (s2 + s3);
   }
   __syncthreads();
   for (int w = blockDim.x / 2; w > 0; w >>= 1) {
@@ -117,6 +124,53 @@ __device__ __forceinline__ void stage_in(const float* __restrict__ src, int coun
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < P; ++j) dst[j] = lds[lds_pad(P * lane + j)];
+  __syncthreads();
+}
+
+// NA arrays at once: every global load is issued before the first LDS write, so one
+// memory round trip covers all of them. lds holds NA consecutive LineBuf<P> buffers.
+template <int P, int NA>
+__device__ __forceinline__ void stage_in_n(const float* const (&src)[NA], const int (&count)[NA],
+                                           bool valid, float* lds, float (&dst)[NA][P],
+                                           int lane) {
+  float t[NA][P];
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int i = lane + 64 * j;
+      t[a][j] = (valid && i < count[a]) ? src[a][i] : 0.0f;
+    }
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int j = 0; j < P; ++j) lds[a * LineBuf<P>::SIZE + lds_pad(lane + 64 * j)] = t[a][j];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int j = 0; j < P; ++j) dst[a][j] = lds[a * LineBuf<P>::SIZE + lds_pad(P * lane + j)];
+  __syncthreads();
+}
+
+// NA arrays out at once (one barrier pair for all of them).
+template <int P, int NA>
+__device__ __forceinline__ void stage_out_n(float* const (&dst)[NA], int count, bool valid,
+                                            float* lds, const float (&v)[NA][P], int lane) {
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int j = 0; j < P; ++j) lds[a * LineBuf<P>::SIZE + lds_pad(P * lane + j)] = v[a][j];
+  __syncthreads();
+  if (valid) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int t = lane + 64 * j;
+        if (t < count) dst[a][t] = lds[a * LineBuf<P>::SIZE + lds_pad(t)];
+      }
+  }
   __syncthreads();
 }
 

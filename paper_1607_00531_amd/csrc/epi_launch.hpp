@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
+
 #include "epi_common.hpp"
 
 namespace epi {
@@ -20,8 +22,9 @@ void launch_pcg_update(hipStream_t s, int P, LineArgs a, int precond, const floa
                        const float* hoff, float* x, float* r, float* z, const float* p,
                        const float* q, double* partial, const DevState* st);
 void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* z,
-                       const float* u, float* w, int* hard_list, double* partial,
-                       DevState* st, int hard_blocks);
+                       const float* u, float* w, int* hard_list, DevState* st, int hard_blocks,
+                       const std::function<void(int)>& before,
+                       const std::function<void()>& after);
 
 // epi_vec.hip
 int flat_blocks(long long n);

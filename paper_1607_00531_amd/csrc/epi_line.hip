@@ -402,25 +402,29 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
                                                     const float* __restrict__ zvec,
                                                     const float* __restrict__ uvec,
                                                     float* __restrict__ wvec, int* hard_list,
-                                                    double* partial, DevState* st) {
+                                                    DevState* st) {
   if (st->admm_done) return;
-  __shared__ float sbuf[EPI_LINE_WAVES][3][LineBuf<P>::SIZE];
+  __shared__ float sbuf[EPI_LINE_WAVES][5][LineBuf<P>::SIZE];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
   const int lc = valid ? line : 0;
   const int NF = a.M + 1;
   const size_t base = (size_t)lc * NF;
-  float* sIp = sbuf[wave][0];
-  float* sIm = sbuf[wave][1];
-  for (int t = lane; t < 64 * P; t += 64) {
-    sIp[lds_pad(t)] = (valid && t < a.M) ? a.Ip[(size_t)lc * a.M + t] : 0.0f;
-    sIm[lds_pad(t)] = (valid && t < a.M) ? a.Im[(size_t)lc * a.M + t] : 0.0f;
-  }
+  const float* srcs[5] = {a.Ip + (size_t)lc * a.M, a.Im + (size_t)lc * a.M, bvec + base,
+                          zvec + base, uvec + base};
+  const int cnt[5] = {a.M, a.M, NF, NF, NF};
+  float v[5][P];
+  stage_in_n<P, 5>(srcs, cnt, valid, &sbuf[wave][0][0], v, lane);
+  const float* sIp = sbuf[wave][0];
+  const float* sIm = sbuf[wave][1];
   float b[P], z[P], u[P];
-  stage_in<P>(bvec + base, NF, valid, sbuf[wave][2], b, lane);
-  stage_in<P>(zvec + base, NF, valid, sbuf[wave][2], z, lane);
-  stage_in<P>(uvec + base, NF, valid, sbuf[wave][2], u, lane);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    b[j] = v[2][j];
+    z[j] = v[3][j];
+    u[j] = v[4][j];
+  }
   const float rho = (float)st->rho;
   float Gd[P], Go[P], c[P], g[P];
   qp_data<P>(a, rho, b, z, u, sIp, sIm, lane, Gd, Go, c, g);
@@ -445,23 +449,27 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
     if (cidx < NF && !(fabsf(x[j]) < 3.0e38f)) bad = true;
   }
   hard = __any(hard);
-  double acc[NQ_ADMM_B] = {0};
   if (bad && valid && lane == 0) atomicAdd(&st->numeric_bad, 1);
   float bn[P], wn[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     bn[j] = b[j] + x[j];
     wn[j] = bn[j] + u[j];
-    if (valid && !hard && P * lane + j < NF) acc[0] += (double)bn[j] * bn[j];
   }
   if (valid && hard && lane == 0) {
     const int idx = atomicAdd(&st->hard_count, 1);
     hard_list[idx] = line;
   }
   const bool wr = valid && !hard;
-  stage_out<P>(bvec + base, NF, wr, sbuf[wave][2], bn, lane);
-  stage_out<P>(wvec + base, NF, wr, sbuf[wave][2], wn, lane);
-  block_partials<NQ_ADMM_B>(acc, partial, blockIdx.x);
+  float* outs[2] = {bvec + base, wvec + base};
+  float ov[2][P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    ov[0][j] = bn[j];
+    ov[1][j] = wn[j];
+  }
+  stage_out_n<P, 2>(outs, NF, wr, &sbuf[wave][2][0], ov, lane);
+
 }
 
 // Primal active-set method for one line (Section 4.2, eq. qp / eq. schurasqp), run by one
@@ -592,13 +600,10 @@ __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __res
                                                         const float* __restrict__ zvec,
                                                         const float* __restrict__ uvec,
                                                         float* __restrict__ wvec,
-                                                        const int* hard_list, double* partial,
-                                                        DevState* st) {
+                                                        const int* hard_list, DevState* st) {
   if (st->admm_done) return;
   const int nhard = st->hard_count;
   if ((int)blockIdx.x >= nhard) {
-    double acc0[1] = {0.0};
-    block_partials<1>(acc0, partial, blockIdx.x);
     return;
   }
   __shared__ float sIp[LineBuf<P>::SIZE], sIm[LineBuf<P>::SIZE], stg[LineBuf<P>::SIZE];
@@ -609,7 +614,6 @@ __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __res
   __shared__ int res_sh;
   const int lane = threadIdx.x;
   const int NF = a.M + 1;
-  double acc[1] = {0.0};
   for (int h = blockIdx.x; h < nhard; h += gridDim.x) {
     const int line = hard_list[h];
     const size_t base = (size_t)line * NF;
@@ -642,14 +646,12 @@ __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __res
       const int i = P * lane + j;
       bn[j] = (i < NF) ? b[j] + x[i] : 0.0f;
       wn[j] = bn[j] + u[j];
-      if (i < NF) acc[0] += (double)bn[j] * bn[j];
     }
     stage_out<P>(bvec + base, NF, true, stg, bn, lane);
     stage_out<P>(wvec + base, NF, true, stg, wn, lane);
     if (lane == 0) atomicMax(&st->max_active, res_sh & 0xffff);
     __syncthreads();
   }
-  block_partials<1>(acc, partial, blockIdx.x);
 }
 
 // ------------------------------------------------------------------------------------
@@ -704,14 +706,18 @@ void launch_pcg_update(hipStream_t s, int P, LineArgs a, int precond, const floa
 }
 
 void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* z,
-                       const float* u, float* w, int* hard_list, double* partial,
-                       DevState* st, int hard_blocks) {
+                       const float* u, float* w, int* hard_list, DevState* st, int hard_blocks,
+                       const std::function<void(int)>& before,
+                       const std::function<void()>& after) {
   const int nb = line_blocks(a);
+  before(0);
   EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep<PP>), dim3(nb), dim3(256), 0, s, a, b, z,
-                                       u, w, hard_list, partial, st));
+                                       u, w, hard_list, st));
+  after();
+  before(1);
   EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep_hard<PP>), dim3(hard_blocks), dim3(64), 0,
-                                       s, a, b, z, u, w, hard_list,
-                                       partial + (size_t)nb * NQ_ADMM_B, st));
+                                       s, a, b, z, u, w, hard_list, st));
+  after();
 }
 
 }  // namespace epi

@@ -64,6 +64,13 @@ class ADMMReport(C.Structure):
                 ("eps_pri", C.POINTER(C.c_double)), ("eps_dual", C.POINTER(C.c_double))]
 
 
+class KernelProfile(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
+
+
+KERNEL_NAMES = ["bstep", "bstep_hard", "dct_axis3", "dct_axis2_fused", "dct_last_epilogue",
+                "finalize"]
+
 _lib = None
 
 
@@ -87,6 +94,9 @@ def lib():
         L.epi_solve_gnpcg.restype = st
         L.epi_solve_admm.argtypes = [vp, vp, vp, vp, C.POINTER(ADMMOpts), C.POINTER(ADMMReport)]
         L.epi_solve_admm.restype = st
+        L.epi_profile_admm.argtypes = [vp, vp, vp, vp, C.POINTER(ADMMOpts), C.POINTER(ADMMReport),
+                                       C.POINTER(KernelProfile)]
+        L.epi_profile_admm.restype = st
         L.epi_destroy.argtypes = [vp]
         L.epi_destroy.restype = None
         L.epi_gn_default_opts.argtypes = [C.POINTER(GNOpts)]
@@ -242,7 +252,9 @@ class Problem:
                     pcg_relres=list(arrs["pcg_relres"][:k]), step=list(arrs["step"][:k]),
                     pcg_iters=list(its[:k]))
 
-    def solve_admm(self, b, z, u, **kw) -> dict:
+    def solve_admm(self, b, z, u, profile: bool = False, **kw) -> dict:
+        """ADMM from the state (b, z, u), updated in place. With profile=True the solve runs
+        through epi_profile_admm and the result carries per-kernel device times."""
         o = ADMMOpts()
         lib().epi_admm_default_opts(C.byref(o))
         for k, v in kw.items():
@@ -252,11 +264,20 @@ class Problem:
         rep = ADMMReport()
         for k, a in arrs.items():
             setattr(rep, k, C.cast(a, C.POINTER(C.c_double)))
-        _check(lib().epi_solve_admm(self._h, self._faces(b), self._faces(z), self._faces(u),
-                                    C.byref(o), C.byref(rep)))
+        if profile:
+            prof = KernelProfile()
+            _check(lib().epi_profile_admm(self._h, self._faces(b), self._faces(z),
+                                          self._faces(u), C.byref(o), C.byref(rep),
+                                          C.byref(prof)))
+        else:
+            _check(lib().epi_solve_admm(self._h, self._faces(b), self._faces(z), self._faces(u),
+                                        C.byref(o), C.byref(rep)))
         k = rep.iters
         out = dict(iters=k, converged=bool(rep.converged), max_active=rep.max_active,
                    hard_lines=int(rep.hard_lines))
         for key, a in arrs.items():
             out[key] = list(a[:k])
+        if profile:
+            out["kernel_ms"] = {n: prof.ms[i] for i, n in enumerate(KERNEL_NAMES)}
+            out["kernel_launches"] = {n: int(prof.launches[i]) for i, n in enumerate(KERNEL_NAMES)}
         return out
