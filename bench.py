@@ -47,6 +47,29 @@ def algorithmic_bytes(M, m2, m3):
     }
 
 
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE summary,
+    or None when the kernel sources changed since those counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "admm_240x200x110_hbm_counters.md")
+    try:
+        txt = open(path).read()
+        blob = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    csrc = os.path.join(ROOT, "paper_1607_00531_amd", "csrc")
+    for fname, h in blob["sources_sha256_16"].items():
+        try:
+            cur = hashlib.sha256(open(os.path.join(csrc, fname), "rb").read()).hexdigest()[:16]
+        except OSError:
+            return None
+        if cur != h:
+            return None
+    rec = blob["per_launch"].get(kernel)
+    return rec["traffic_bytes"] if rec else None
+
+
 def percentile(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -93,6 +116,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gn", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=MAX_ITER,
+                    help="ADMM iteration cap per solve (short profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -126,7 +153,7 @@ def main():
         def one(i):
             for t in state:
                 t.zero_()
-            return probs[i % len(probs)].solve_admm(*state, rho=RHO, max_iter=MAX_ITER,
+            return probs[i % len(probs)].solve_admm(*state, rho=RHO, max_iter=args.max_iter,
                                                     eps_abs=0.0, eps_rel=TOL, check_every=16)
 
         for i in range(warmup):
@@ -144,6 +171,14 @@ def main():
         total = time.perf_counter() - t_start
         return probs, total, lat, iters, conv
 
+    if args.copy_calibration:
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 536870912 bytes read and written by one copy kernel")
+
     log("timing the mixed-precision solver")
     probs, total, lat, iters, conv = run("mixed", args.steps, args.warmup)
     value = args.steps / total
@@ -152,7 +187,7 @@ def main():
     # per-kernel device time of one profiled solve (HIP events on the library stream)
     for t in state:
         t.zero_()
-    prof = probs[0].solve_admm(*state, profile=True, rho=RHO, max_iter=MAX_ITER, eps_abs=0.0,
+    prof = probs[0].solve_admm(*state, profile=True, rho=RHO, max_iter=args.max_iter, eps_abs=0.0,
                                eps_rel=TOL, check_every=16)
     nbytes = algorithmic_bytes(M, m2, m3)
     kernels = {}
@@ -168,8 +203,9 @@ def main():
     dom = max((k for k in kernels if nbytes[k]), key=lambda k: kernels[k]["total_ms"])
     peak = 8000.0
     ach = kernels[dom]["GB_s"]
+    traffic = counter_traffic(dom)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": peak, "unit": "GB/s",
-                "frac": round(ach / peak, 4), "traffic": None,
+                "frac": round(ach / peak, 4), "traffic": traffic,
                 "bytes_per_launch": nbytes[dom], "avg_launch_us": round(kernels[dom]["avg_us"], 2)}
     iter_us = 1e3 * sum(k["total_ms"] for k in kernels.values()) / max(prof["iters"], 1)
     log(f"profile: {json.dumps(kernels)}")

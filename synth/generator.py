@@ -293,10 +293,10 @@ def generate(seed: int, m_user: Sequence[int], pe_axis: int, *, noise: float = 0
 # The five workload configurations (sizes, PE axis, solver parameters)
 # --------------------------------------------------------------------------------------
 CONFIGS = {
-    "c1_2d_64": dict(m_user=(64, 64), pe_axis=1, alpha=50.0, beta=10.0, rho=1e3, iters=20),
-    "c2_3d_128x128x64": dict(m_user=(128, 128, 64), pe_axis=1, alpha=50.0, beta=10.0,
+    "2d_64x64": dict(m_user=(64, 64), pe_axis=1, alpha=50.0, beta=10.0, rho=1e3, iters=20),
+    "3d_128x128x64": dict(m_user=(128, 128, 64), pe_axis=1, alpha=50.0, beta=10.0,
                              rho=1e3, iters=30),
-    "c3_3d_240x200x110": dict(m_user=(240, 200, 110), pe_axis=0, alpha=50.0, beta=10.0,
+    "3d_240x200x110": dict(m_user=(240, 200, 110), pe_axis=0, alpha=50.0, beta=10.0,
                               rho=1e3, iters=30),
 }
 

@@ -158,7 +158,7 @@ def test_admm_trajectory(shape, pe, alpha, iters, prec):
 
 
 def test_admm_stopping_rule_matches_oracle():
-    v = config_volume("c1_2d_64", 0)
+    v = config_volume("2d_64x64", 0)
     P = O.make_problem(v.Ip, v.Im, v.h, 50.0)
     bo, zo, uo, ro = O.solve_admm(P, rho=1e3, max_iter=300, eps_abs=0.0, eps_rel=1e-3)
     assert ro.converged
@@ -193,9 +193,9 @@ def test_admm_results_independent_of_polling_and_resumable():
 
 @pytest.mark.parametrize("precond", ["block", "jacobi", "none"])
 def test_gnpcg_trajectory_config_c1(precond):
-    v = config_volume("c1_2d_64", 0)
-    alpha = CONFIGS["c1_2d_64"]["alpha"]
-    its = CONFIGS["c1_2d_64"]["iters"]
+    v = config_volume("2d_64x64", 0)
+    alpha = CONFIGS["2d_64x64"]["alpha"]
+    its = CONFIGS["2d_64x64"]["iters"]
     P = O.make_problem(v.Ip, v.Im, v.h, alpha)
     bo, ro = O.solve_gnpcg(P, max_iter=its, use_stopping=False, precond=precond)
     with _problem(v, alpha, "fp32") as pr:
