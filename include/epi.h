@@ -29,6 +29,7 @@
  *   field violates the constraint (|D1 b| < 1 for GN-PCG, |D1 b| <= 1 for ADMM).
  *   EPI_ENUMERIC: NaN/Inf met in the inputs or the iteration. EPI_EHIP: a HIP runtime
  *   error (message carries the HIP error string). EPI_ENOMEM: device allocation failed.
+ *   EPI_EBUSY (batched engine): no slot or HBM budget free right now; nothing changed.
  *   Hitting an iteration cap is EPI_OK with converged = 0.
  * Limits. M + 1 <= 512 faces per PE line; m2 <= 256 and m3 <= 256 (the DCT axes).
  */
@@ -50,7 +51,8 @@ typedef enum {
   EPI_EINFEASIBLE = 3,
   EPI_ENUMERIC = 4,
   EPI_EHIP = 5,
-  EPI_ENOTSUP = 6
+  EPI_ENOTSUP = 6,
+  EPI_EBUSY = 7
 } epi_status;
 
 /* Arithmetic of the z-step DCT products. FP32: float32 matrix-core products (the plain
@@ -193,6 +195,55 @@ epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
 epi_status epi_profile_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
                             const epi_admm_opts* opts, epi_admm_report* rep,
                             epi_kernel_profile* prof);
+
+/* ------------------------------------------------------------------------------------
+ * Continuous-batching ADMM engine: the served form of the Section 4.2 solver. Up to
+ * max_slots volumes of different sizes (and 2D/3D) are resident at once; one ADMM
+ * iteration of all running volumes is one persistent launch per kernel class over their
+ * PE lines and DCT tiles, captured in a hipGraph; each volume has its own stopping flag
+ * (eq. admmStop) and iteration cap, and a volume's arithmetic does not depend on the other
+ * volumes in the batch. Finished volumes free their slot for new requests (continuous
+ * batching). All volumes of one batch use one z-step precision.
+ * ------------------------------------------------------------------------------------ */
+typedef struct epi_batch epi_batch;
+
+/* Create an engine with max_slots (<= 128) slots, an admission limit hbm_budget_bytes on
+ * the summed epi_batch_footprint of resident volumes, the z-step precision
+ * (epi_precision) and iters_per_step ADMM iterations per epi_batch_step call. Kernels
+ * run on a private stream ordered after `stream` (a hipStream_t or NULL). */
+epi_status epi_batch_create(int32_t max_slots, int64_t hbm_budget_bytes, int32_t precision,
+                            int32_t iters_per_step, void* stream, epi_batch** out);
+
+/* Device bytes one request occupies while resident: its images and state arrays
+ * (borrowed from the caller) plus the workspace the engine allocates for it (three n-float
+ * arrays, DCT tables, partial sums, residual histories). -1 for a NULL grid. */
+int64_t epi_batch_footprint(const epi_grid* grid, int32_t max_iter);
+
+/* Admit one request: geometry and weights (grid; its precision field is replaced by the
+ * engine's), the image pair (N floats each, canonical layout), and its ADMM state arrays
+ * d_b, d_z, d_u (n floats each, caller-owned, read and written in place until the slot
+ * is released; |D1 b| <= 1 required, else EPI_EINFEASIBLE). opts: rho, eps_abs, eps_rel,
+ * max_iter as for epi_solve_admm (sqp_iters must be 1; check_every is not used). On
+ * success *slot is the slot index. EPI_EBUSY: no free slot or not enough budget. */
+epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const float* d_Iplus,
+                           const float* d_Iminus, float* d_b, float* d_z, float* d_u,
+                           const epi_admm_opts* opts, int32_t* slot);
+
+/* Run iters_per_step ADMM iterations of every running volume (one graph replay; volumes
+ * admitted since the last call join here), synchronise, and report in *running how many
+ * volumes are still iterating. */
+epi_status epi_batch_step(epi_batch* bt, int32_t* running);
+
+/* *finished = 1 once the slot's volume has converged or reached max_iter; then rep (may
+ * be NULL) receives the report and histories as from epi_solve_admm. */
+epi_status epi_batch_poll(epi_batch* bt, int32_t slot, int32_t* finished, epi_admm_report* rep);
+
+/* Free a slot (finished or not): its workspace is released and its footprint leaves the
+ * budget. The caller's arrays are not touched. */
+epi_status epi_batch_release(epi_batch* bt, int32_t slot);
+
+/* Destroy the engine and every slot's workspace (NULL is a no-op). */
+void epi_batch_destroy(epi_batch* bt);
 
 /* Release the handle and its workspace (NULL is a no-op). */
 void epi_destroy(epi_problem* p);

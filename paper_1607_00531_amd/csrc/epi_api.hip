@@ -15,6 +15,7 @@
 #include "epi.h"
 #include "epi_common.hpp"
 #include "epi_launch.hpp"
+#include "epi_internal.hpp"
 
 using namespace epi;
 
@@ -25,7 +26,7 @@ using namespace epi;
 // ------------------------------------------------------------------------------------
 static thread_local std::string g_err;
 
-static epi_status fail(epi_status s, const char* fmt, ...) {
+epi_status epi::fail(epi_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -70,7 +71,6 @@ struct epi_problem {
   float *g = nullptr, *hd = nullptr, *ho = nullptr, *x = nullptr, *r = nullptr, *zz = nullptr,
         *p = nullptr, *q = nullptr;
   double* partial = nullptr;     // general partial sums
-  double* partial_b = nullptr;   // ADMM b-step (fast + hard kernels)
   double* partial_e = nullptr;   // ADMM z/u epilogue
   size_t partial_cap = 0;
   DevState* st = nullptr;
@@ -78,9 +78,7 @@ struct epi_problem {
   int* hard_list = nullptr;
   int hard_blocks = 0;
   // DCT tables (packed MFMA fragments), eigenvalues
-  void *A3f = nullptr, *A3i = nullptr, *A2f = nullptr, *A2i = nullptr;
-  int RT2 = 0, KS2 = 0, RT3 = 0, KS3 = 0;
-  float *lam2 = nullptr, *lam3 = nullptr;
+  DctTables tab;
   double* hist = nullptr;
   int hist_cap = 0;
   // captured ADMM chunk
@@ -225,9 +223,9 @@ static std::vector<float> pack_f32(const std::vector<double>& A, int m, int& RT,
   return out;
 }
 
-static epi_status upload_matrix(epi_problem* p, const std::vector<double>& A, int m, void** dst,
+static epi_status upload_matrix(int precision, const std::vector<double>& A, int m, void** dst,
                                 int& RT, int& KS) {
-  if (p->grid.precision == EPI_PREC_MIXED) {
+  if (precision == EPI_PREC_MIXED) {
     auto v = pack_bf16(A, m, RT, KS);
     HIPCHK(hipMalloc(dst, v.size() * sizeof(uint16_t)));
     HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
@@ -239,31 +237,39 @@ static epi_status upload_matrix(epi_problem* p, const std::vector<double>& A, in
   return EPI_OK;
 }
 
-static epi_status build_tables(epi_problem* p) {
+epi_status epi::build_dct_tables(int m2, int m3, double h2, double h3, int precision,
+                                 DctTables* t) {
   std::vector<double> C, Ct;
   int RT, KS;
   for (int axis = 2; axis <= 3; ++axis) {
-    const int m = axis == 2 ? p->m2 : p->m3;
-    const double h = p->grid.h[axis - 1];
+    const int m = axis == 2 ? m2 : m3;
+    const double h = axis == 2 ? h2 : h3;
     dct_host(m, C);
     Ct.assign((size_t)m * m, 0.0);
     for (int a = 0; a < m; ++a)
       for (int j = 0; j < m; ++j) Ct[(size_t)j * m + a] = C[(size_t)a * m + j];
     epi_status s;
     if (axis == 2) {
-      if ((s = upload_matrix(p, C, m, &p->A2f, RT, KS)) != EPI_OK) return s;
-      if ((s = upload_matrix(p, Ct, m, &p->A2i, p->RT2, p->KS2)) != EPI_OK) return s;
+      if ((s = upload_matrix(precision, C, m, &t->A2f, RT, KS)) != EPI_OK) return s;
+      if ((s = upload_matrix(precision, Ct, m, &t->A2i, t->RT2, t->KS2)) != EPI_OK) return s;
     } else {
-      if ((s = upload_matrix(p, C, m, &p->A3f, RT, KS)) != EPI_OK) return s;
-      if ((s = upload_matrix(p, Ct, m, &p->A3i, p->RT3, p->KS3)) != EPI_OK) return s;
+      if ((s = upload_matrix(precision, C, m, &t->A3f, RT, KS)) != EPI_OK) return s;
+      if ((s = upload_matrix(precision, Ct, m, &t->A3i, t->RT3, t->KS3)) != EPI_OK) return s;
     }
     std::vector<float> lam(m);
     for (int j = 0; j < m; ++j) lam[j] = (float)((2.0 - 2.0 * cos(M_PI * j / m)) / (h * h));
-    float** dl = axis == 2 ? &p->lam2 : &p->lam3;
+    float** dl = axis == 2 ? &t->lam2 : &t->lam3;
     HIPCHK(hipMalloc(dl, m * sizeof(float)));
     HIPCHK(hipMemcpy(*dl, lam.data(), m * sizeof(float), hipMemcpyHostToDevice));
   }
   return EPI_OK;
+}
+
+void epi::free_dct_tables(DctTables* t) {
+  void* bufs[] = {t->A2f, t->A2i, t->A3f, t->A3i, t->lam2, t->lam3};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  *t = DctTables();
 }
 
 static void free_graph(epi_problem* p) {
@@ -279,10 +285,10 @@ EPI_API void epi_destroy(epi_problem* p) {
   if (p->exec) (void)hipStreamSynchronize(p->exec);
   free_graph(p);
   void* bufs[] = {p->w, p->t1, p->t2, p->g, p->hd, p->ho, p->x, p->r, p->zz, p->p, p->q,
-                  p->partial, p->partial_b, p->partial_e, p->st, p->hard_list, p->A3f,
-                  p->A3i, p->A2f, p->A2i, p->lam2, p->lam3, p->hist};
+                  p->partial, p->partial_e, p->st, p->hard_list, p->hist};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
+  free_dct_tables(&p->tab);
   if (p->st_h) (void)hipHostFree(p->st_h);
   for (hipEvent_t e : p->prof_ev) (void)hipEventDestroy(e);
   if (p->ev_in) (void)hipEventDestroy(p->ev_in);
@@ -291,16 +297,15 @@ EPI_API void epi_destroy(epi_problem* p) {
   delete p;
 }
 
-static int dct_tiles_axis3(const epi_problem* p) {
-  const long long Q = (long long)p->m2 * (p->M + 1);
+int epi::tiles_axis3(int M, int m2) {
+  const long long Q = (long long)m2 * (M + 1);
   return (int)((Q + 63) / 64);
 }
-static int dct_tiles_axis2(const epi_problem* p) { return p->m3 * ((p->M + 1 + 63) / 64); }
+int epi::tiles_axis2(int M, int m3) { return m3 * ((M + 1 + 63) / 64); }
+static int dct_tiles_axis3(const epi_problem* p) { return tiles_axis3(p->M, p->m2); }
+static int dct_tiles_axis2(const epi_problem* p) { return tiles_axis2(p->M, p->m3); }
 
-static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float* Im, void* stream,
-                             epi_problem** out) {
-  if (!grid || !Ip || !Im || !out) return fail(EPI_EINVAL, "null argument");
-  *out = nullptr;
+epi_status epi::validate_grid(const epi_grid* grid) {
   if (grid->ndim != 2 && grid->ndim != 3) return fail(EPI_EINVAL, "ndim must be 2 or 3");
   const int M = grid->m[0], m2 = grid->m[1], m3 = grid->m[2];
   if (M < 2 || m2 < 1 || m3 < 1) return fail(EPI_EINVAL, "cell counts must be M >= 2, m2, m3 >= 1");
@@ -313,7 +318,36 @@ static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float*
     return fail(EPI_EINVAL, "alpha, beta, gamma must be >= 0");
   if (grid->precision != EPI_PREC_FP32 && grid->precision != EPI_PREC_MIXED)
     return fail(EPI_EINVAL, "unknown precision %d", grid->precision);
+  return EPI_OK;
+}
 
+LineArgs epi::make_line_args(const epi_grid* grid, const float* Ip, const float* Im) {
+  LineArgs a{};
+  a.Ip = Ip;
+  a.Im = Im;
+  a.M = grid->m[0];
+  a.m2 = grid->m[1];
+  a.m3 = grid->m[2];
+  a.L = a.m2 * a.m3;
+  a.hp = (float)grid->h[0];
+  a.inv_hp = (float)(1.0 / grid->h[0]);
+  a.inv_h2sq = (float)(1.0 / (grid->h[1] * grid->h[1]));
+  a.inv_h3sq = (float)(1.0 / (grid->h[2] * grid->h[2]));
+  a.v = (float)(grid->h[0] * grid->h[1] * grid->h[2]);
+  a.alpha = (float)grid->alpha;
+  a.beta = (float)grid->beta;
+  a.gamma = (float)grid->gamma;
+  a.nblk = line_blocks(a);
+  return a;
+}
+
+static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float* Im, void* stream,
+                             epi_problem** out) {
+  if (!grid || !Ip || !Im || !out) return fail(EPI_EINVAL, "null argument");
+  *out = nullptr;
+  epi_status vs = validate_grid(grid);
+  if (vs != EPI_OK) return vs;
+  const int M = grid->m[0], m2 = grid->m[1], m3 = grid->m[2];
   epi_problem* p = new epi_problem();
   p->grid = *grid;
   p->M = M;
@@ -327,22 +361,8 @@ static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float*
   p->Ip = Ip;
   p->Im = Im;
   p->user = (hipStream_t)stream;
+  p->la = make_line_args(grid, Ip, Im);
   LineArgs& a = p->la;
-  a.Ip = Ip;
-  a.Im = Im;
-  a.M = M;
-  a.m2 = m2;
-  a.m3 = m3;
-  a.L = p->L;
-  a.hp = (float)grid->h[0];
-  a.inv_hp = (float)(1.0 / grid->h[0]);
-  a.inv_h2sq = (float)(1.0 / (grid->h[1] * grid->h[1]));
-  a.inv_h3sq = (float)(1.0 / (grid->h[2] * grid->h[2]));
-  a.v = (float)p->v;
-  a.alpha = (float)grid->alpha;
-  a.beta = (float)grid->beta;
-  a.gamma = (float)grid->gamma;
-  a.nblk = line_blocks(a);
   *out = p;
 
   static bool lds_set = false;
@@ -365,14 +385,13 @@ static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float*
   cap = std::max(cap, (size_t)std::max(dct_tiles_axis2(p), dct_tiles_axis3(p)) * 4);
   p->partial_cap = cap;
   HIPCHK(hipMalloc(&p->partial, cap * sizeof(double)));
-  HIPCHK(hipMalloc(&p->partial_b, ((size_t)lb + p->hard_blocks) * sizeof(double)));
   HIPCHK(hipMalloc(&p->partial_e, (size_t)std::max(dct_tiles_axis2(p), dct_tiles_axis3(p)) * NQ_ADMM_E * sizeof(double)));
   HIPCHK(hipMalloc(&p->st, sizeof(DevState)));
   HIPCHK(hipHostMalloc((void**)&p->st_h, sizeof(DevState), hipHostMallocDefault));
   memset(p->st_h, 0, sizeof(DevState));
   HIPCHK(hipMemcpy(p->st, p->st_h, sizeof(DevState), hipMemcpyHostToDevice));
   HIPCHK(hipMalloc(&p->hard_list, (size_t)p->L * sizeof(int)));
-  epi_status s = build_tables(p);
+  epi_status s = build_dct_tables(m2, m3, grid->h[1], grid->h[2], grid->precision, &p->tab);
   if (s != EPI_OK) return s;
 
   // the images must be finite
@@ -448,43 +467,53 @@ EPI_API epi_status epi_objective(epi_problem* p, const float* d_b, int32_t with_
 // ------------------------------------------------------------------------------------
 // z-step passes
 // ------------------------------------------------------------------------------------
-static GemmArgs gemm_axis3(const epi_problem* p, const float* in, float* out, const void* A) {
+GemmArgs epi::make_gemm_axis3(int M, int m2, int m3, float alpha, const DctTables& t,
+                              const float* in, float* out, bool inverse, const DevState* st) {
   GemmArgs g{};
   g.in = in;
   g.out = out;
-  g.rows = p->m3;
-  g.ncol = p->m2 * (p->M + 1);
-  g.ld = (long long)p->m2 * (p->M + 1);
+  g.rows = m3;
+  g.ncol = m2 * (M + 1);
+  g.ld = (long long)m2 * (M + 1);
   g.bstride = 0;
   g.nbatch = 1;
   g.col_tiles = (g.ncol + 63) / 64;
-  g.RT = p->RT3;
-  g.KS = p->KS3;
-  g.A1 = A;
+  g.RT = t.RT3;
+  g.KS = t.KS3;
+  g.A1 = inverse ? t.A3i : t.A3f;
   g.A2 = nullptr;
-  g.alpha = (float)p->grid.alpha;
-  g.st = p->st;
+  g.alpha = alpha;
+  g.st = st;
   return g;
 }
-static GemmArgs gemm_axis2(const epi_problem* p, const float* in, float* out) {
+
+GemmArgs epi::make_gemm_axis2(int M, int m2, int m3, float alpha, const DctTables& t,
+                              const float* in, float* out, const DevState* st) {
   GemmArgs g{};
   g.in = in;
   g.out = out;
-  g.rows = p->m2;
-  g.ncol = p->M + 1;
-  g.ld = p->M + 1;
-  g.bstride = (long long)p->m2 * (p->M + 1);
-  g.nbatch = p->m3;
+  g.rows = m2;
+  g.ncol = M + 1;
+  g.ld = M + 1;
+  g.bstride = (long long)m2 * (M + 1);
+  g.nbatch = m3;
   g.col_tiles = (g.ncol + 63) / 64;
-  g.RT = p->RT2;
-  g.KS = p->KS2;
-  g.A1 = p->A2f;
-  g.A2 = p->A2i;
-  g.lam_row = p->lam2;
-  g.lam_batch = p->lam3;
-  g.alpha = (float)p->grid.alpha;
-  g.st = p->st;
+  g.RT = t.RT2;
+  g.KS = t.KS2;
+  g.A1 = t.A2f;
+  g.A2 = t.A2i;
+  g.lam_row = t.lam2;
+  g.lam_batch = t.lam3;
+  g.alpha = alpha;
+  g.st = st;
   return g;
+}
+
+static GemmArgs gemm_axis3(const epi_problem* p, const float* in, float* out, bool inverse) {
+  return make_gemm_axis3(p->M, p->m2, p->m3, (float)p->grid.alpha, p->tab, in, out, inverse, p->st);
+}
+static GemmArgs gemm_axis2(const epi_problem* p, const float* in, float* out) {
+  return make_gemm_axis2(p->M, p->m2, p->m3, (float)p->grid.alpha, p->tab, in, out, p->st);
 }
 
 // z = smoothness solve of w; with admm != 0 the last pass performs the u-step epilogue
@@ -509,7 +538,7 @@ static epi_status launch_zstep(epi_problem* p, const float* w, float* z, int adm
     CHKLAUNCH();
     return EPI_OK;
   }
-  GemmArgs g1 = gemm_axis3(p, w, p->t1, p->A3f);
+  GemmArgs g1 = gemm_axis3(p, w, p->t1, false);
   g1.done = done;
   prof_begin(p, EPI_K_DCT_AXIS3);
   launch_dct_axis3(p->exec, prec, g1);
@@ -521,7 +550,7 @@ static epi_status launch_zstep(epi_problem* p, const float* w, float* z, int adm
   launch_dct_axis2_fused(p->exec, prec, g2);
   prof_end(p);
   CHKLAUNCH();
-  GemmArgs g3 = gemm_axis3(p, p->t2, z, p->A3i);
+  GemmArgs g3 = gemm_axis3(p, p->t2, z, true);
   g3.done = done;
   if (admm) {
     g3.epi = 1;

@@ -1,0 +1,589 @@
+// Continuous-batching ADMM engine (the served form of the Section 4.2 solver).
+//
+// Up to EPI_BATCH_MAX volumes of different sizes are resident at once. One ADMM iteration
+// of all of them is one persistent launch per kernel class: the b-step walks the PE lines
+// of every running volume with P faces per lane, the z-step kernels walk the 64-column DCT
+// tiles of every running volume of a tile class, and one finalisation launch evaluates
+// every volume's float64 stopping test. The work lists live in device memory, so the
+// captured graph of an iteration stays valid while volumes come and go; it is captured
+// again only when the set of kernel classes changes. Each volume keeps its own stopping
+// flag; a finished volume's work items return at once and its slot is reused by the next
+// admitted request. Per-volume arithmetic (and its reduction order) does not depend on
+// the other volumes in the batch.
+#include <hip/hip_runtime.h>
+
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "epi.h"
+#include "epi_common.hpp"
+#include "epi_dct_body.hpp"
+#include "epi_device.hpp"
+#include "epi_internal.hpp"
+#include "epi_launch.hpp"
+#include "epi_line_body.hpp"
+
+#define EPI_API extern "C" __attribute__((visibility("default")))
+
+namespace epi {
+
+#define BATCH_LINE_GRID 2048
+#define BATCH_HARD_GRID 128
+#define BATCH_DCT_GRID 1024
+
+// index k of the range holding item i: first[k] <= i < first[k+1]
+__device__ __forceinline__ int range_find(const RangeTable& T, int i) {
+  int lo = 0, hi = T.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (T.first[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_batch_bstep(BatchDev* bd, int cls) {
+  const RangeTable& T = bd->bt[cls];
+  if (T.n == 0) return;
+  const int total = T.first[T.n];
+  const int units = (total + EPI_LINE_WAVES - 1) / EPI_LINE_WAVES;
+  __shared__ float sbuf[EPI_LINE_WAVES][5][LineBuf<P>::SIZE];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int unit = blockIdx.x; unit < units; unit += gridDim.x) {
+    const int gl = unit * EPI_LINE_WAVES + wave;
+    const int k = range_find(T, gl < total ? gl : total - 1);
+    const int slot = T.slot[k];
+    const BatchSlotDev& S = bd->slots[slot];
+    const bool valid = gl < total && !S.st->admm_done;
+    const int line = gl < total ? gl - T.first[k] : 0;
+    const bool hard = bstep_line_body<P>(S.la, (float)S.st->rho, S.b, S.z, S.u, S.w,
+                                         valid ? line : 0, valid, &sbuf[wave][0][0], lane,
+                                         &S.st->numeric_bad);
+    if (valid && hard && lane == 0) {
+      const int idx = atomicAdd(&bd->hard_count[cls], 1);
+      bd->hard_list[cls][idx] = HardItem{slot, line};
+      atomicAdd(&S.st->hard_count, 1);
+    }
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_batch_hard(BatchDev* bd, int cls) {
+  const int nh = bd->hard_count[cls];
+  if ((int)blockIdx.x >= nh) return;
+  __shared__ HardLds<P> L;
+  for (int h = blockIdx.x; h < nh; h += gridDim.x) {
+    const HardItem it = bd->hard_list[cls][h];
+    const BatchSlotDev& S = bd->slots[it.slot];
+    hard_line_body<P>(S.la, (float)S.st->rho, S.b, S.z, S.u, S.w, it.line, L, threadIdx.x,
+                      &S.st->max_active);
+  }
+}
+
+template <int PREC, bool FUSED, int EPI, int KSM, int SLOTS>
+__global__ __launch_bounds__(256) void k_batch_dct(BatchDev* bd, int cls, int pass) {
+  const RangeTable& T = bd->dt[cls];
+  if (T.n == 0) return;
+  const int total = T.first[T.n];
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int k = range_find(T, t);
+    const BatchSlotDev& S = bd->slots[T.slot[k]];
+    if (S.st->admm_done) continue;
+    const GemmArgs& g = pass == 1 ? S.g1 : (pass == 2 ? S.g2 : S.g3);
+    const int local = t - T.first[k];
+    const int batch = local / g.col_tiles;
+    const int c0 = (local % g.col_tiles) * DCT_NT;
+    if (PREC == 1)
+      dct_bf16_body<FUSED, EPI, KSM, SLOTS>(g, batch, c0, local,
+                                            reinterpret_cast<unsigned short*>(lds_raw));
+    else
+      dct_f32_body<FUSED, EPI, KSM * 8, SLOTS>(g, batch, c0, local,
+                                               reinterpret_cast<float*>(lds_raw));
+  }
+}
+
+// one workgroup per slot: float64 reduction of the last pass's sums and the stopping test
+__global__ __launch_bounds__(256) void k_batch_finalize(BatchDev* bd) {
+  if (blockIdx.x == 0 && threadIdx.x <= EPI_PMAX) bd->hard_count[threadIdx.x] = 0;
+  const BatchSlotDev& S = bd->slots[blockIdx.x];
+  if (!S.active || S.st->admm_done) return;
+  __shared__ double sums[NQ_ADMM_E];
+  reduce_partials<NQ_ADMM_E>(S.last_partial, S.last_ntiles, sums);
+  if (threadIdx.x == 0) admm_finalize(S.st, sums, S.hist, S.hist_len);
+}
+
+// ------------------------------------------------------------------------------------
+// host runtime
+// ------------------------------------------------------------------------------------
+static size_t dct_class_lds(int prec, bool small) {
+  GemmArgs g{};
+  g.KS = small ? (prec == 1 ? 4 : 32) : (prec == 1 ? 8 : 64);
+  g.RT = small ? 8 : 16;
+  return dct_lds_bytes(prec, g);
+}
+
+template <bool FUSED, int EPI>
+static void launch_batch_dct(hipStream_t s, int prec, BatchDev* bd, int cls, int pass, bool small) {
+  const size_t lds = dct_class_lds(prec, small);
+  const dim3 grid(BATCH_DCT_GRID), blk(256);
+  if (prec == 1) {
+    if (small) hipLaunchKernelGGL((k_batch_dct<1, FUSED, EPI, 4, 2>), grid, blk, lds, s, bd, cls, pass);
+    else hipLaunchKernelGGL((k_batch_dct<1, FUSED, EPI, 8, 4>), grid, blk, lds, s, bd, cls, pass);
+  } else {
+    if (small) hipLaunchKernelGGL((k_batch_dct<0, FUSED, EPI, 4, 2>), grid, blk, lds, s, bd, cls, pass);
+    else hipLaunchKernelGGL((k_batch_dct<0, FUSED, EPI, 8, 4>), grid, blk, lds, s, bd, cls, pass);
+  }
+}
+
+template <bool FUSED, int EPI>
+static hipError_t set_batch_lds(int big) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_batch_dct<1, FUSED, EPI, 8, 4>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_batch_dct<0, FUSED, EPI, 8, 4>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, big);
+}
+
+}  // namespace epi
+
+using namespace epi;
+
+#define BHIPCHK(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? EPI_ENOMEM : EPI_EHIP, "%s: %s (%s:%d)",  \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                   \
+  } while (0)
+
+namespace {
+
+struct SlotHost {
+  bool used = false, finished = false;
+  epi_grid grid{};
+  int M = 0, m2 = 0, m3 = 0, L = 0, P = 0;
+  long long n = 0, N = 0;
+  const float *Ip = nullptr, *Im = nullptr;
+  float *b = nullptr, *z = nullptr, *u = nullptr;
+  float *w = nullptr, *t1 = nullptr, *t2 = nullptr;
+  double* partial = nullptr;
+  double* hist = nullptr;
+  int hist_len = 0;
+  DctTables tab;
+  int64_t footprint = 0;
+  epi_admm_opts opts{};
+};
+
+int64_t workspace_bytes(const epi_grid* g, int max_iter) {
+  const long long M = g->m[0], m2 = g->m[1], m3 = g->m[2];
+  const long long n = (M + 1) * m2 * m3;
+  const long long tiles = std::max<long long>(tiles_axis3((int)M, (int)m2), tiles_axis2((int)M, (int)m3));
+  const long long part = std::max<long long>(tiles * NQ_ADMM_E, 4096);
+  const long long tables = 4 * (m2 * m2 + m3 * m3) * 4 + 4 * (m2 + m3);
+  return 3 * n * 4 + part * 8 + 4LL * std::max(max_iter, 1) * 8 + tables;
+}
+
+}  // namespace
+
+struct epi_batch {
+  int max_slots = 0, precision = 1, iters_per_step = 8;
+  int64_t budget = 0, used_bytes = 0;
+  hipStream_t user = nullptr, exec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  BatchDev* d_bd = nullptr;
+  BatchDev* h_bd = nullptr;
+  DevState* d_st = nullptr;
+  DevState* h_st = nullptr;
+  HardItem* hard[EPI_PMAX + 1] = {nullptr};
+  int hard_cap[EPI_PMAX + 1] = {0};
+  std::vector<SlotHost> slots;
+  bool dirty = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint32_t graph_key = 0xffffffffu;
+  int running = 0;
+};
+
+static void batch_free_slot(SlotHost& s) {
+  void* bufs[] = {s.w, s.t1, s.t2, s.partial, s.hist};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  free_dct_tables(&s.tab);
+  s = SlotHost();
+}
+
+EPI_API int64_t epi_batch_footprint(const epi_grid* grid, int32_t max_iter) {
+  if (!grid) return -1;
+  const long long M = grid->m[0], m2 = grid->m[1], m3 = grid->m[2];
+  const long long n = (M + 1) * m2 * m3, N = M * m2 * m3;
+  return 4 * (2 * N + 3 * n) + workspace_bytes(grid, max_iter);
+}
+
+EPI_API void epi_batch_destroy(epi_batch* bt) {
+  if (!bt) return;
+  if (bt->exec) (void)hipStreamSynchronize(bt->exec);
+  if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  for (auto& s : bt->slots)
+    if (s.used) batch_free_slot(s);
+  for (int c = 0; c <= EPI_PMAX; ++c)
+    if (bt->hard[c]) (void)hipFree(bt->hard[c]);
+  if (bt->d_bd) (void)hipFree(bt->d_bd);
+  if (bt->d_st) (void)hipFree(bt->d_st);
+  if (bt->h_bd) (void)hipHostFree(bt->h_bd);
+  if (bt->h_st) (void)hipHostFree(bt->h_st);
+  if (bt->ev_in) (void)hipEventDestroy(bt->ev_in);
+  if (bt->ev_out) (void)hipEventDestroy(bt->ev_out);
+  if (bt->exec) (void)hipStreamDestroy(bt->exec);
+  delete bt;
+}
+
+static epi_status batch_create_impl(int32_t max_slots, int64_t budget, int32_t precision,
+                                    int32_t iters_per_step, void* stream, epi_batch** out) {
+  if (!out) return fail(EPI_EINVAL, "null argument");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > EPI_BATCH_MAX)
+    return fail(EPI_EINVAL, "max_slots must be in [1, %d]", EPI_BATCH_MAX);
+  if (precision != EPI_PREC_FP32 && precision != EPI_PREC_MIXED)
+    return fail(EPI_EINVAL, "unknown precision %d", precision);
+  if (iters_per_step < 1) return fail(EPI_EINVAL, "iters_per_step must be >= 1");
+  if (budget <= 0) return fail(EPI_EINVAL, "hbm_budget_bytes must be > 0");
+  epi_batch* bt = new epi_batch();
+  *out = bt;
+  bt->max_slots = max_slots;
+  bt->budget = budget;
+  bt->precision = precision;
+  bt->iters_per_step = iters_per_step;
+  bt->user = (hipStream_t)stream;
+  bt->slots.resize(max_slots);
+  int dev = 0;
+  BHIPCHK(hipGetDevice(&dev));
+  BHIPCHK(hipSetDevice(dev));
+  BHIPCHK(hipStreamCreateWithFlags(&bt->exec, hipStreamNonBlocking));
+  (void)dct_set_lds_limits();
+  BHIPCHK((set_batch_lds<true, 0>(80 * 1024)));
+  BHIPCHK((set_batch_lds<true, 1>(80 * 1024)));
+  BHIPCHK((set_batch_lds<false, 0>(80 * 1024)));
+  BHIPCHK((set_batch_lds<false, 1>(80 * 1024)));
+  BHIPCHK(hipEventCreateWithFlags(&bt->ev_in, hipEventDisableTiming));
+  BHIPCHK(hipEventCreateWithFlags(&bt->ev_out, hipEventDisableTiming));
+  BHIPCHK(hipMalloc(&bt->d_bd, sizeof(BatchDev)));
+  BHIPCHK(hipHostMalloc((void**)&bt->h_bd, sizeof(BatchDev), hipHostMallocDefault));
+  memset(bt->h_bd, 0, sizeof(BatchDev));
+  BHIPCHK(hipMemcpy(bt->d_bd, bt->h_bd, sizeof(BatchDev), hipMemcpyHostToDevice));
+  BHIPCHK(hipMalloc(&bt->d_st, sizeof(DevState) * EPI_BATCH_MAX));
+  BHIPCHK(hipHostMalloc((void**)&bt->h_st, sizeof(DevState) * EPI_BATCH_MAX, hipHostMallocDefault));
+  memset(bt->h_st, 0, sizeof(DevState) * EPI_BATCH_MAX);
+  BHIPCHK(hipMemcpy(bt->d_st, bt->h_st, sizeof(DevState) * EPI_BATCH_MAX, hipMemcpyHostToDevice));
+  return EPI_OK;
+}
+
+EPI_API epi_status epi_batch_create(int32_t max_slots, int64_t hbm_budget_bytes, int32_t precision,
+                                    int32_t iters_per_step, void* stream, epi_batch** out) {
+  epi_status s = batch_create_impl(max_slots, hbm_budget_bytes, precision, iters_per_step, stream, out);
+  if (s != EPI_OK && out && *out) {
+    epi_batch_destroy(*out);
+    *out = nullptr;
+  }
+  return s;
+}
+
+static void batch_enter(epi_batch* bt) {
+  (void)hipEventRecord(bt->ev_in, bt->user);
+  (void)hipStreamWaitEvent(bt->exec, bt->ev_in, 0);
+}
+static void batch_leave(epi_batch* bt) {
+  (void)hipEventRecord(bt->ev_out, bt->exec);
+  (void)hipStreamWaitEvent(bt->user, bt->ev_out, 0);
+}
+
+EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const float* d_Iplus,
+                                   const float* d_Iminus, float* d_b, float* d_z, float* d_u,
+                                   const epi_admm_opts* opts, int32_t* slot_out) {
+  if (!bt || !grid || !d_Iplus || !d_Iminus || !d_b || !d_z || !d_u || !opts || !slot_out)
+    return fail(EPI_EINVAL, "null argument");
+  *slot_out = -1;
+  epi_status vs = validate_grid(grid);
+  if (vs != EPI_OK) return vs;
+  if (!(opts->rho > 0.0) || opts->max_iter < 1 || opts->sqp_iters != 1)
+    return fail(EPI_EINVAL, "batched ADMM needs rho > 0, max_iter >= 1, sqp_iters = 1");
+  const int64_t fp = epi_batch_footprint(grid, opts->max_iter);
+  int sid = -1;
+  for (int i = 0; i < bt->max_slots; ++i)
+    if (!bt->slots[i].used) {
+      sid = i;
+      break;
+    }
+  if (sid < 0) return fail(EPI_EBUSY, "no free slot (%d resident)", bt->max_slots);
+  if (bt->used_bytes + fp > bt->budget)
+    return fail(EPI_EBUSY, "HBM budget: %lld resident + %lld requested > %lld", (long long)bt->used_bytes,
+                (long long)fp, (long long)bt->budget);
+  SlotHost& s = bt->slots[sid];
+  s = SlotHost();
+  s.grid = *grid;
+  s.grid.precision = bt->precision;
+  s.M = grid->m[0];
+  s.m2 = grid->m[1];
+  s.m3 = grid->m[2];
+  s.L = s.m2 * s.m3;
+  s.P = (s.M + 1 + 63) / 64;
+  s.n = (long long)(s.M + 1) * s.L;
+  s.N = (long long)s.M * s.L;
+  s.Ip = d_Iplus;
+  s.Im = d_Iminus;
+  s.b = d_b;
+  s.z = d_z;
+  s.u = d_u;
+  s.opts = *opts;
+  s.footprint = fp;
+  s.hist_len = opts->max_iter;
+  s.used = true;   // from here on a failure releases the slot
+  auto undo = [&](epi_status st) {
+    batch_free_slot(s);
+    return st;
+  };
+  const size_t nb = (size_t)s.n * sizeof(float);
+  if (hipMalloc(&s.w, nb) != hipSuccess || hipMalloc(&s.t1, nb) != hipSuccess ||
+      hipMalloc(&s.t2, nb) != hipSuccess)
+    return undo(fail(EPI_ENOMEM, "slot workspace"));
+  const long long tiles = std::max(tiles_axis3(s.M, s.m2), tiles_axis2(s.M, s.m3));
+  const size_t part = (size_t)std::max<long long>(tiles * NQ_ADMM_E, 4096);
+  if (hipMalloc(&s.partial, part * sizeof(double)) != hipSuccess ||
+      hipMalloc(&s.hist, (size_t)4 * s.hist_len * sizeof(double)) != hipSuccess)
+    return undo(fail(EPI_ENOMEM, "slot buffers"));
+  epi_status ts = build_dct_tables(s.m2, s.m3, grid->h[1], grid->h[2], bt->precision, &s.tab);
+  if (ts != EPI_OK) return undo(ts);
+  // feasibility of the starting field and the slot's stopping state
+  batch_enter(bt);
+  DevState* dst = bt->d_st + sid;
+  DevState* hst = bt->h_st + sid;
+  const LineArgs la = make_line_args(&s.grid, s.Ip, s.Im);
+  launch_count_violations(bt->exec, la, d_b, 1.0f + 1e-5f, s.partial);
+  FinArgs f{};
+  f.kind = FIN_DOT;
+  f.partial = s.partial;
+  f.nb1 = flat_blocks(s.N);
+  launch_finalize(bt->exec, f, dst);
+  if (hipGetLastError() != hipSuccess) return undo(fail(EPI_EHIP, "admission check launch"));
+  if (hipStreamSynchronize(bt->exec) != hipSuccess) return undo(fail(EPI_EHIP, "sync"));
+  DevState tmp;
+  if (hipMemcpy(&tmp, dst, sizeof(DevState), hipMemcpyDeviceToHost) != hipSuccess)
+    return undo(fail(EPI_EHIP, "state copy"));
+  if (tmp.gTd > 0.0) {
+    batch_leave(bt);
+    return undo(fail(EPI_EINFEASIBLE, "starting field has %.0f cells with |D1 b| > 1", tmp.gTd));
+  }
+  memset(hst, 0, sizeof(DevState));
+  hst->rho = opts->rho;
+  hst->eps_abs = opts->eps_abs;
+  hst->eps_rel = opts->eps_rel;
+  hst->sqrt_n = sqrt((double)s.n);
+  hst->v = grid->h[0] * grid->h[1] * grid->h[2];
+  hst->admm_max = opts->max_iter;
+  if (hipMemcpy(dst, hst, sizeof(DevState), hipMemcpyHostToDevice) != hipSuccess)
+    return undo(fail(EPI_EHIP, "state init"));
+  batch_leave(bt);
+  bt->used_bytes += fp;
+  bt->dirty = true;
+  *slot_out = sid;
+  return EPI_OK;
+}
+
+// work tables of the running volumes, uploaded to the device; returns the class key
+static epi_status batch_rebuild(epi_batch* bt, uint32_t* key) {
+  BatchDev* h = bt->h_bd;
+  memset(h, 0, sizeof(BatchDev));
+  int need[EPI_PMAX + 1] = {0};
+  uint32_t k = 0;
+  bt->running = 0;
+  for (int i = 0; i < bt->max_slots; ++i) {
+    SlotHost& s = bt->slots[i];
+    if (!s.used || s.finished) continue;
+    bt->running += 1;
+    BatchSlotDev& d = h->slots[i];
+    d.la = make_line_args(&s.grid, s.Ip, s.Im);
+    d.b = s.b;
+    d.z = s.z;
+    d.u = s.u;
+    d.w = s.w;
+    d.st = bt->d_st + i;
+    d.active = 1;
+    d.hist = s.hist;
+    d.hist_len = s.hist_len;
+    const float alpha = (float)s.grid.alpha;
+    const bool three = s.m3 > 1;
+    d.three_pass = three;
+    auto add = [&](RangeTable& T, int items) {
+      T.slot[T.n] = i;
+      T.first[T.n + 1] = T.first[T.n] + items;
+      T.n += 1;
+    };
+    add(h->bt[s.P], s.L);
+    need[s.P] += s.L;
+    k |= 1u << s.P;
+    const int small3 = s.m3 <= 128 ? 0 : 1, small2 = s.m2 <= 128 ? 0 : 1;
+    if (three) {
+      d.g1 = make_gemm_axis3(s.M, s.m2, s.m3, alpha, s.tab, s.w, s.t1, false, d.st);
+      d.g2 = make_gemm_axis2(s.M, s.m2, s.m3, alpha, s.tab, s.t1, s.t2, d.st);
+      d.g3 = make_gemm_axis3(s.M, s.m2, s.m3, alpha, s.tab, s.t2, s.z, true, d.st);
+      d.g3.epi = 1;
+      d.g3.b = s.b;
+      d.g3.z = s.z;
+      d.g3.u = s.u;
+      d.g3.partial = s.partial;
+      d.last_ntiles = d.g3.nbatch * d.g3.col_tiles;
+      d.last_partial = s.partial;
+      add(h->dt[0 + small3], d.g1.nbatch * d.g1.col_tiles);
+      add(h->dt[2 + small2], d.g2.nbatch * d.g2.col_tiles);
+      add(h->dt[6 + small3], d.g3.nbatch * d.g3.col_tiles);
+      k |= 1u << (16 + small3);
+      k |= 1u << (16 + 2 + small2);
+      k |= 1u << (16 + 6 + small3);
+    } else {
+      d.g2 = make_gemm_axis2(s.M, s.m2, s.m3, alpha, s.tab, s.w, s.z, d.st);
+      d.g2.epi = 1;
+      d.g2.b = s.b;
+      d.g2.z = s.z;
+      d.g2.u = s.u;
+      d.g2.partial = s.partial;
+      d.last_ntiles = d.g2.nbatch * d.g2.col_tiles;
+      d.last_partial = s.partial;
+      add(h->dt[4 + small2], d.g2.nbatch * d.g2.col_tiles);
+      k |= 1u << (16 + 4 + small2);
+    }
+  }
+  for (int c = 1; c <= EPI_PMAX; ++c) {
+    if (need[c] > bt->hard_cap[c]) {
+      if (bt->hard[c]) BHIPCHK(hipFree(bt->hard[c]));
+      bt->hard[c] = nullptr;
+      BHIPCHK(hipMalloc(&bt->hard[c], (size_t)need[c] * sizeof(HardItem)));
+      bt->hard_cap[c] = need[c];
+    }
+    h->hard_list[c] = bt->hard[c];
+  }
+  BHIPCHK(hipMemcpyAsync(bt->d_bd, h, sizeof(BatchDev), hipMemcpyHostToDevice, bt->exec));
+  *key = k;
+  return EPI_OK;
+}
+
+static void batch_iteration(epi_batch* bt, uint32_t key) {
+  hipStream_t s = bt->exec;
+  BatchDev* bd = bt->d_bd;
+  for (int P = 1; P <= EPI_PMAX; ++P) {
+    if (!(key & (1u << P))) continue;
+    switch (P) {
+      case 1: hipLaunchKernelGGL(k_batch_bstep<1>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
+      case 2: hipLaunchKernelGGL(k_batch_bstep<2>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
+      case 3: hipLaunchKernelGGL(k_batch_bstep<3>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
+      case 4: hipLaunchKernelGGL(k_batch_bstep<4>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
+      case 5: hipLaunchKernelGGL(k_batch_bstep<5>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
+      case 6: hipLaunchKernelGGL(k_batch_bstep<6>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
+      case 7: hipLaunchKernelGGL(k_batch_bstep<7>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
+      default: hipLaunchKernelGGL(k_batch_bstep<8>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
+    }
+  }
+  for (int P = 1; P <= EPI_PMAX; ++P) {
+    if (!(key & (1u << P))) continue;
+    switch (P) {
+      case 1: hipLaunchKernelGGL(k_batch_hard<1>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
+      case 2: hipLaunchKernelGGL(k_batch_hard<2>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
+      case 3: hipLaunchKernelGGL(k_batch_hard<3>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
+      case 4: hipLaunchKernelGGL(k_batch_hard<4>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
+      case 5: hipLaunchKernelGGL(k_batch_hard<5>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
+      case 6: hipLaunchKernelGGL(k_batch_hard<6>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
+      case 7: hipLaunchKernelGGL(k_batch_hard<7>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
+      default: hipLaunchKernelGGL(k_batch_hard<8>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
+    }
+  }
+  const int prec = bt->precision;
+  for (int c = 0; c < 8; ++c) {
+    if (!(key & (1u << (16 + c)))) continue;
+    const bool small = (c & 1) == 0;
+    if (c < 2) launch_batch_dct<false, 0>(s, prec, bd, c, 1, small);
+    else if (c < 4) launch_batch_dct<true, 0>(s, prec, bd, c, 2, small);
+    else if (c < 6) launch_batch_dct<true, 1>(s, prec, bd, c, 2, small);
+    else launch_batch_dct<false, 1>(s, prec, bd, c, 3, small);
+  }
+  hipLaunchKernelGGL(k_batch_finalize, dim3(bt->max_slots), dim3(256), 0, s, bd);
+}
+
+EPI_API epi_status epi_batch_step(epi_batch* bt, int32_t* running) {
+  if (!bt) return fail(EPI_EINVAL, "null argument");
+  batch_enter(bt);
+  if (bt->dirty) {
+    uint32_t key = 0;
+    epi_status s = batch_rebuild(bt, &key);
+    if (s != EPI_OK) return s;
+    bt->dirty = false;
+    if (key != bt->graph_key && bt->running > 0) {
+      if (bt->gexec) BHIPCHK(hipGraphExecDestroy(bt->gexec));
+      if (bt->graph) BHIPCHK(hipGraphDestroy(bt->graph));
+      bt->gexec = nullptr;
+      bt->graph = nullptr;
+      BHIPCHK(hipStreamBeginCapture(bt->exec, hipStreamCaptureModeThreadLocal));
+      for (int i = 0; i < bt->iters_per_step; ++i) batch_iteration(bt, key);
+      hipError_t e1 = hipGetLastError();
+      hipError_t e2 = hipStreamEndCapture(bt->exec, &bt->graph);
+      if (e1 != hipSuccess || e2 != hipSuccess)
+        return fail(EPI_EHIP, "graph capture: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+      BHIPCHK(hipGraphInstantiate(&bt->gexec, bt->graph, nullptr, nullptr, 0));
+      bt->graph_key = key;
+    }
+  }
+  if (bt->running > 0) {
+    BHIPCHK(hipGraphLaunch(bt->gexec, bt->exec));
+    BHIPCHK(hipMemcpyAsync(bt->h_st, bt->d_st, sizeof(DevState) * bt->max_slots,
+                           hipMemcpyDeviceToHost, bt->exec));
+    BHIPCHK(hipStreamSynchronize(bt->exec));
+    for (int i = 0; i < bt->max_slots; ++i) {
+      SlotHost& s = bt->slots[i];
+      if (s.used && !s.finished && bt->h_st[i].admm_done) {
+        s.finished = true;
+        bt->dirty = true;
+        bt->running -= 1;
+      }
+    }
+  }
+  batch_leave(bt);
+  if (running) *running = bt->running;
+  return EPI_OK;
+}
+
+EPI_API epi_status epi_batch_poll(epi_batch* bt, int32_t slot, int32_t* finished,
+                                  epi_admm_report* rep) {
+  if (!bt || !finished) return fail(EPI_EINVAL, "null argument");
+  if (slot < 0 || slot >= bt->max_slots || !bt->slots[slot].used)
+    return fail(EPI_EINVAL, "slot %d is not in use", slot);
+  SlotHost& s = bt->slots[slot];
+  *finished = s.finished;
+  if (!s.finished || !rep) return EPI_OK;
+  const DevState& h = bt->h_st[slot];
+  const int iters = h.admm_iter;
+  rep->iters = iters;
+  rep->converged = h.admm_done == 1 && h.numeric_bad == 0;
+  rep->max_active = h.max_active;
+  rep->hard_lines = h.hard_total;
+  rep->status = h.numeric_bad ? EPI_ENUMERIC : EPI_OK;
+  double* outs[4] = {rep->r_pri, rep->r_dual, rep->eps_pri, rep->eps_dual};
+  for (int k = 0; k < 4; ++k)
+    if (outs[k] && iters > 0)
+      BHIPCHK(hipMemcpy(outs[k], s.hist + (size_t)k * s.hist_len,
+                        std::min(iters, s.hist_len) * sizeof(double), hipMemcpyDeviceToHost));
+  return EPI_OK;
+}
+
+EPI_API epi_status epi_batch_release(epi_batch* bt, int32_t slot) {
+  if (!bt) return fail(EPI_EINVAL, "null argument");
+  if (slot < 0 || slot >= bt->max_slots || !bt->slots[slot].used)
+    return fail(EPI_EINVAL, "slot %d is not in use", slot);
+  BHIPCHK(hipStreamSynchronize(bt->exec));
+  SlotHost& s = bt->slots[slot];   // a running volume may be released (cancelled)
+  bt->used_bytes -= s.footprint;
+  batch_free_slot(s);
+  bt->dirty = true;
+  return EPI_OK;
+}

@@ -76,4 +76,44 @@ struct GemmArgs {
   const int* done;
 };
 
+// ------------------------------------------------------------------------------------
+// Batched (multi-volume) engine: device-side tables read by the persistent kernels
+// ------------------------------------------------------------------------------------
+#define EPI_BATCH_MAX 128   // resident volumes (slots) per batch
+
+// Work items of one kernel class: the items of slot slot[k] are [first[k], first[k+1]).
+struct RangeTable {
+  int n, pad;
+  int slot[EPI_BATCH_MAX];
+  int first[EPI_BATCH_MAX + 1];
+};
+
+// One resident volume: its geometry, state arrays (caller-owned, resident), workspace,
+// stopping state and the three z-step products (2D: only g2, carrying the epilogue).
+struct BatchSlotDev {
+  LineArgs la;
+  float *b, *z, *u, *w;
+  DevState* st;
+  GemmArgs g1, g2, g3;
+  int three_pass, active;
+  double* hist;
+  int hist_len;
+  int last_ntiles;
+  const double* last_partial;
+};
+
+struct HardItem {
+  int slot, line;
+};
+
+// b-step classes by faces per lane P (index P); DCT classes: 0/1 pass 1 (rows <= 128 /
+// <= 256), 2/3 pass 2 of 3D volumes, 4/5 pass 2 of 2D volumes (with epilogue), 6/7 pass 3.
+struct BatchDev {
+  BatchSlotDev slots[EPI_BATCH_MAX];
+  RangeTable bt[EPI_PMAX + 1];
+  RangeTable dt[8];
+  int hard_count[EPI_PMAX + 1];
+  HardItem* hard_list[EPI_PMAX + 1];
+};
+
 }  // namespace epi

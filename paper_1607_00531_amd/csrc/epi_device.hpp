@@ -91,6 +91,37 @@ __device__ __forceinline__ void reduce_partials(const double* partial, int nb, d
   __syncthreads();
 }
 
+// The float64 stopping test of ADMM (eq. admmStop) at the newest iterates, from the sums
+// |b-z|^2, |z_old-z|^2, |z|^2, |u|^2 and |b|^2 of the last z-step pass.
+__device__ __forceinline__ void admm_finalize(DevState* st, const double* sums, double* hist,
+                                              int hist_len) {
+  const double b2 = sums[4];
+  const double rho = st->rho;
+  const double rpri = sqrt(sums[0]);
+  const double rdual = rho * st->v * sqrt(sums[1]);
+  const double nb = sqrt(b2), nz = sqrt(sums[2]), nu = sqrt(sums[3]);
+  const double epri = st->sqrt_n * st->eps_abs + st->eps_rel * (nb > nz ? nb : nz);
+  const double edual = st->sqrt_n * st->eps_abs + st->eps_rel * rho * st->v * nu;
+  const int it = st->admm_iter;
+  if (it < hist_len) {
+    hist[it] = rpri;
+    hist[hist_len + it] = rdual;
+    hist[2 * hist_len + it] = epri;
+    hist[3 * hist_len + it] = edual;
+  }
+  st->admm_iter = it + 1;
+  st->hard_total += st->hard_count;
+  st->hard_count = 0;
+  const bool finite = (rpri == rpri) && (rdual == rdual) && rpri < 1e300 && rdual < 1e300;
+  if (!finite || st->numeric_bad) {
+    st->numeric_bad += 1;
+    st->admm_done = 1;
+  } else if (rpri <= epri && rdual <= edual) {
+    st->admm_done = 1;
+  } else if (st->admm_iter >= st->admm_max) {
+    st->admm_done = 2;   // iteration cap: later launches of this solve are no-ops
+  }
+}
 // Workgroups are dealt round-robin over the 8 XCDs; remap so that each XCD (and its L2)
 // walks one contiguous range of logical block indices.
 __device__ __forceinline__ int xcd_remap(int bid, int nblk) {

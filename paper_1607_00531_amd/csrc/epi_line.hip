@@ -7,87 +7,9 @@
 #include "epi_device.hpp"
 #include "epi_common.hpp"
 #include "epi_launch.hpp"
+#include "epi_line_body.hpp"
 
 namespace epi {
-
-// 1D linear interpolation of the cell-centred samples of one line held in LDS at index
-// coordinate c + disp (sample c sits at index c); zero outside the M samples; derivative
-// with respect to the physical PE coordinate from the segment [k, k+1], k = floor(c + disp)
-// (the right-hand segment at a knot). The floor is taken of the displacement alone and
-// the integer cell index added afterwards: rounding c + disp in float32 would move small
-// displacements (|disp| < ulp(c) / 2) onto the knot and pick the wrong segment.
-__device__ __forceinline__ void interp_lds(const float* sT, int M, int c, float disp,
-                                           float inv_hp, float& val, float& der) {
-  disp = fminf(fmaxf(disp, -(float)(2 * M + 4)), (float)(2 * M + 4));
-  const float fl = floorf(disp);
-  const int k = c + (int)fl;
-  const float f = disp - fl;
-  if (k < -1 || k > M - 1) {
-    val = 0.0f;
-    der = 0.0f;
-    return;
-  }
-  const float t0 = (k >= 0) ? sT[lds_pad(k)] : 0.0f;
-  const float t1 = (k + 1 <= M - 1) ? sT[lds_pad(k + 1)] : 0.0f;
-  val = fmaf(f, t1 - t0, t0);
-  der = (t1 - t0) * inv_hp;
-}
-
-// Per-cell quantities of the residual for the cells c = P*lane + j (zero for c >= M):
-// g = D1 b, r = I+(x + A b)(1 + g) - I-(x - A b)(1 - g) and the two Jacobian entries
-// dr_c/db_c = Jl, dr_c/db_{c+1} = Jr.
-template <int P>
-struct Cells {
-  float g[P], r[P], Jl[P], Jr[P];
-};
-
-template <int P>
-__device__ __forceinline__ void eval_cells(const LineArgs& a, const float (&b)[P],
-                                           const float* sIp, const float* sIm, int lane,
-                                           Cells<P>& C) {
-  const float bnext = shfl_down0(b[0], 1, lane);
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    const int c = P * lane + j;
-    const float bR = (j < P - 1) ? b[j + 1] : bnext;
-    if (c < a.M) {
-      const float aidx = 0.5f * (b[j] + bR) * a.inv_hp;
-      const float g = (bR - b[j]) * a.inv_hp;
-      float ipv, ipd, imv, imd;
-      interp_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
-      interp_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
-      const float gp = 1.0f + g, gm = 1.0f - g;
-      C.g[j] = g;
-      C.r[j] = ipv * gp - imv * gm;
-      const float Sd = ipd * gp + imd * gm, Tv = ipv + imv;
-      C.Jl[j] = 0.5f * Sd - Tv * a.inv_hp;
-      C.Jr[j] = 0.5f * Sd + Tv * a.inv_hp;
-    } else {
-      C.g[j] = 0.0f;
-      C.r[j] = 0.0f;
-      C.Jl[j] = 0.0f;
-      C.Jr[j] = 0.0f;
-    }
-  }
-}
-
-// Value of a per-cell array at cell (face index - 1) for each local face j.
-template <int P>
-__device__ __forceinline__ void prev_cell(const float (&x)[P], float (&out)[P], int lane) {
-  const float pl = shfl_up0(x[P - 1], 1, lane);
-  out[0] = pl;
-#pragma unroll
-  for (int j = 1; j < P; ++j) out[j] = x[j - 1];
-}
-
-// Number of transverse neighbours divided by h^2 (diagonal of D2'D2 + D3'D3) of line
-// (j, k).
-__device__ __forceinline__ float cross_diag(const LineArgs& a, int jj, int kk) {
-  float s = 0.0f;
-  if (a.m2 > 1) s += ((jj > 0) + (jj < a.m2 - 1)) * a.inv_h2sq;
-  if (a.m3 > 1) s += ((kk > 0) + (kk < a.m3 - 1)) * a.inv_h3sq;
-  return s;
-}
 
 // ------------------------------------------------------------------------------------
 // Objective / gradient / Gauss-Newton pack (eq. D, eq. S, eq. P, eq. dJ, eq. dJGN).
@@ -349,54 +271,6 @@ __global__ __launch_bounds__(256) void k_pcg_update(LineArgs a, int precond,
   block_partials<NQ_PCG>(acc, partial, blockIdx.x);
 }
 
-// ------------------------------------------------------------------------------------
-// ADMM b-step (Section 4.2): per PE line, QP data at b^k
-//   c = grad D(b^k) + alpha v D1'D1 b^k + rho v (b^k - z^k + u^k)
-//   G = H_D(b^k) + alpha v D1'D1 + rho v I          (SPD tridiagonal)
-// and the QP  min 1/2 x'Gx + c'x  s.t.  -1 <= D1 (b^k + x) <= 1.
-// ------------------------------------------------------------------------------------
-template <int P>
-__device__ __forceinline__ void qp_data(const LineArgs& a, float rho, const float (&b)[P],
-                                        const float (&z)[P], const float (&u)[P],
-                                        const float* sIp, const float* sIm, int lane,
-                                        float (&Gd)[P], float (&Go)[P], float (&c)[P],
-                                        float (&g)[P]) {
-  Cells<P> C;
-  eval_cells<P>(a, b, sIp, sIm, lane, C);
-  float Jrr[P], rpJ[P], gprev[P], JrPrev[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) Jrr[j] = C.Jr[j] * C.r[j];
-  prev_cell<P>(Jrr, rpJ, lane);
-  prev_cell<P>(C.g, gprev, lane);
-  prev_cell<P>(C.Jr, JrPrev, lane);
-  const int NF = a.M + 1;
-  const float rv = rho * a.v;
-  const float qa = a.alpha * a.v * a.inv_hp * a.inv_hp;
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    const int i = P * lane + j;
-    g[j] = C.g[j];
-    if (i < NF) {
-      c[j] = a.v * (C.Jl[j] * C.r[j] + rpJ[j]) +
-             a.alpha * a.v * (gprev[j] - C.g[j]) * a.inv_hp + rv * (b[j] - z[j] + u[j]);
-      const float ncell = (float)((i < a.M) + (i >= 1));
-      Gd[j] = a.v * (C.Jl[j] * C.Jl[j] + JrPrev[j] * JrPrev[j]) + qa * ncell + rv;
-      Go[j] = (i < a.M) ? a.v * C.Jl[j] * C.Jr[j] - qa : 0.0f;
-    } else {
-      c[j] = 0.0f;
-      Gd[j] = 1.0f;
-      Go[j] = 0.0f;
-    }
-  }
-}
-
-// Tolerances of the float32 active-set logic (relative to the unit bound on |D1 b|).
-#define EPI_TOL_ACTIVE 4e-6f
-
-// Fast path: lines whose starting working set is empty and whose unconstrained step
-// -G^{-1} c keeps |D1 b| <= 1 are solved by that single tridiagonal solve (the active-set
-// method terminates there). Other lines are appended to hard_list, left untouched, and
-// solved by k_admm_bstep_hard. Writes b^{k+1} (in place) and w = b^{k+1} + u^k.
 template <int P>
 __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restrict__ bvec,
                                                     const float* __restrict__ zvec,
@@ -408,193 +282,16 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
-  const int lc = valid ? line : 0;
-  const int NF = a.M + 1;
-  const size_t base = (size_t)lc * NF;
-  const float* srcs[5] = {a.Ip + (size_t)lc * a.M, a.Im + (size_t)lc * a.M, bvec + base,
-                          zvec + base, uvec + base};
-  const int cnt[5] = {a.M, a.M, NF, NF, NF};
-  float v[5][P];
-  stage_in_n<P, 5>(srcs, cnt, valid, &sbuf[wave][0][0], v, lane);
-  const float* sIp = sbuf[wave][0];
-  const float* sIm = sbuf[wave][1];
-  float b[P], z[P], u[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    b[j] = v[2][j];
-    z[j] = v[3][j];
-    u[j] = v[4][j];
-  }
-  const float rho = (float)st->rho;
-  float Gd[P], Go[P], c[P], g[P];
-  qp_data<P>(a, rho, b, z, u, sIp, sIm, lane, Gd, Go, c, g);
-  float x[P];
-  bool hard = false;
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    x[j] = -c[j];
-    if (P * lane + j < a.M && fabsf(g[j]) >= 1.0f - EPI_TOL_ACTIVE) hard = true;
-  }
-  wave_tridiag_solve<P>(Gd, Go, x, lane);
-  const float xnext = shfl_down0(x[0], 1, lane);
-  bool bad = false;
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    const int cidx = P * lane + j;
-    if (cidx < a.M) {
-      const float xr = (j < P - 1) ? x[j + 1] : xnext;
-      const float gn = g[j] + (xr - x[j]) * a.inv_hp;
-      if (!(fabsf(gn) <= 1.0f)) hard = true;   // also catches NaN
-    }
-    if (cidx < NF && !(fabsf(x[j]) < 3.0e38f)) bad = true;
-  }
-  hard = __any(hard);
-  if (bad && valid && lane == 0) atomicAdd(&st->numeric_bad, 1);
-  float bn[P], wn[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    bn[j] = b[j] + x[j];
-    wn[j] = bn[j] + u[j];
-  }
+  const bool hard = bstep_line_body<P>(a, (float)st->rho, bvec, zvec, uvec, wvec,
+                                       valid ? line : 0, valid, &sbuf[wave][0][0], lane,
+                                       &st->numeric_bad);
   if (valid && hard && lane == 0) {
     const int idx = atomicAdd(&st->hard_count, 1);
     hard_list[idx] = line;
   }
-  const bool wr = valid && !hard;
-  float* outs[2] = {bvec + base, wvec + base};
-  float ov[2][P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    ov[0][j] = bn[j];
-    ov[1][j] = wn[j];
-  }
-  stage_out_n<P, 2>(outs, NF, wr, &sbuf[wave][2][0], ov, lane);
-
 }
 
-// Primal active-set method for one line (Section 4.2, eq. qp / eq. schurasqp), run by one
-// lane on LDS arrays. The equality-constrained subproblem of a working set W (active
-// cells fix D1(x + p) to +-1) is solved in the null space of A_W: faces joined by active
-// cells move together, which leaves a tridiagonal system in one unknown per group. This
-// gives the same KKT point (p, lambda) as the Schur-complement formulation; the
-// multiplier of an active cell is a running sum of G p + G x + c over its group.
-//   p = 0 (or a full step was just taken) and lambda >= 0: optimal;
-//   some lambda < 0: drop the most negative one (lowest cell on ties);
-//   otherwise step to the first blocking constraint and add every blocking constraint.
-// st_: 0 free, 1 lower bound active (D1 b = -1), 2 upper bound active (D1 b = +1).
-__device__ int active_set_serial(int N, float hp, const float* Gd, const float* Go,
-                                 const float* c, const float* g0, float* x, float* p,
-                                 float* o, float* q, float* rd, float* ro, float* rr,
-                                 int* grp, unsigned char* st_, int max_iter) {
-  const int Mc = N - 1;
-  const float inv_h = 1.0f / hp;
-  for (int i = 0; i < N; ++i) x[i] = 0.0f;
-  for (int cc = 0; cc < Mc; ++cc)
-    st_[cc] = (g0[cc] <= -1.0f + EPI_TOL_ACTIVE) ? 1 : (g0[cc] >= 1.0f - EPI_TOL_ACTIVE ? 2 : 0);
-  int it = 0;
-  for (; it < max_iter; ++it) {
-    // groups and fixed offsets inside each group
-    grp[0] = 0;
-    o[0] = 0.0f;
-    for (int i = 1; i < N; ++i) {
-      const int cc = i - 1;
-      if (st_[cc]) {
-        grp[i] = grp[i - 1];
-        const float target = (st_[cc] == 1) ? -1.0f : 1.0f;
-        const float gx = g0[cc] + (x[i] - x[i - 1]) * inv_h;
-        o[i] = o[i - 1] + hp * (target - gx);
-      } else {
-        grp[i] = grp[i - 1] + 1;
-        o[i] = 0.0f;
-      }
-    }
-    const int ng = grp[N - 1] + 1;
-    for (int t = 0; t < ng; ++t) {
-      rd[t] = 0.0f;
-      ro[t] = 0.0f;
-      rr[t] = 0.0f;
-    }
-    for (int i = 0; i < N; ++i) {
-      float gx = Gd[i] * x[i], go = Gd[i] * o[i];
-      if (i > 0) { gx += Go[i - 1] * x[i - 1]; go += Go[i - 1] * o[i - 1]; }
-      if (i < N - 1) { gx += Go[i] * x[i + 1]; go += Go[i] * o[i + 1]; }
-      q[i] = gx + c[i];
-      const int t = grp[i];
-      rr[t] -= q[i] + go;
-      rd[t] += Gd[i];
-      if (i < N - 1) {
-        if (grp[i + 1] == t) rd[t] += 2.0f * Go[i];
-        else ro[t] = Go[i];
-      }
-    }
-    // Thomas on the group system
-    for (int t = 1; t < ng; ++t) {
-      const float m = ro[t - 1] / rd[t - 1];
-      rd[t] -= m * ro[t - 1];
-      rr[t] -= m * rr[t - 1];
-    }
-    rr[ng - 1] /= rd[ng - 1];
-    for (int t = ng - 2; t >= 0; --t) rr[t] = (rr[t] - ro[t] * rr[t + 1]) / rd[t];
-    float pmax = 0.0f;
-    for (int i = 0; i < N; ++i) {
-      p[i] = rr[grp[i]] + o[i];
-      pmax = fmaxf(pmax, fabsf(p[i]));
-    }
-    // multipliers of the active cells
-    float lam_min = 0.0f;
-    int lam_arg = -1;
-    float run = 0.0f;
-    for (int i = 0; i < N; ++i) {
-      if (i == 0 || st_[i - 1] == 0) run = 0.0f;
-      float wv = Gd[i] * p[i] + q[i];
-      if (i > 0) wv += Go[i - 1] * p[i - 1];
-      if (i < N - 1) wv += Go[i] * p[i + 1];
-      run += wv;
-      if (i < Mc && st_[i]) {
-        const float lam = hp * (st_[i] == 1 ? 1.0f : -1.0f) * (-run);
-        if (lam < lam_min) {
-          lam_min = lam;
-          lam_arg = i;
-        }
-      }
-    }
-    if (pmax > 1e-6f * hp) {
-      float rmin = 3.0e38f;
-      for (int cc = 0; cc < Mc; ++cc) {
-        if (st_[cc]) continue;
-        const float dp = (p[cc + 1] - p[cc]) * inv_h;
-        const float gx = g0[cc] + (x[cc + 1] - x[cc]) * inv_h;
-        float ratio = 3.0e38f;
-        if (dp < 0.0f) ratio = (-1.0f - gx) / dp;
-        else if (dp > 0.0f) ratio = (1.0f - gx) / dp;
-        rmin = fminf(rmin, ratio);
-      }
-      const float sigma = (rmin < 1.0f) ? fmaxf(rmin, 0.0f) : 1.0f;
-      for (int i = 0; i < N; ++i) x[i] = fmaf(sigma, p[i], x[i]);
-      if (rmin < 1.0f) {
-        const float lim = rmin + 1e-6f * fmaxf(1.0f, fabsf(rmin));
-        for (int cc = 0; cc < Mc; ++cc) {
-          if (st_[cc]) continue;
-          const float dp = (p[cc + 1] - p[cc]) * inv_h;
-          const float gx0 = g0[cc] + (x[cc + 1] - x[cc]) * inv_h - sigma * dp;
-          float ratio = 3.0e38f;
-          if (dp < 0.0f) ratio = (-1.0f - gx0) / dp;
-          else if (dp > 0.0f) ratio = (1.0f - gx0) / dp;
-          if (ratio <= lim) st_[cc] = (dp < 0.0f) ? 1 : 2;
-        }
-        continue;
-      }
-    }
-    if (lam_arg < 0) break;       // every multiplier >= 0: optimal
-    st_[lam_arg] = 0;             // drop the most negative multiplier
-  }
-  int nact = 0;
-  for (int cc = 0; cc < Mc; ++cc) nact += st_[cc] != 0;
-  return nact | (it << 16);
-}
-
-// Hard lines of the b-step: one wavefront per line, QP data computed wave-parallel, the
-// active-set loop by lane 0. Writes b^{k+1} and w for those lines and their |b|^2.
+// Hard lines of the b-step: one wavefront per line (see hard_line_body).
 template <int P>
 __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __restrict__ bvec,
                                                         const float* __restrict__ zvec,
@@ -603,55 +300,11 @@ __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __res
                                                         const int* hard_list, DevState* st) {
   if (st->admm_done) return;
   const int nhard = st->hard_count;
-  if ((int)blockIdx.x >= nhard) {
-    return;
-  }
-  __shared__ float sIp[LineBuf<P>::SIZE], sIm[LineBuf<P>::SIZE], stg[LineBuf<P>::SIZE];
-  __shared__ float Gd[64 * P], Go[64 * P], cv[64 * P], g0[64 * P], x[64 * P], p[64 * P],
-      o[64 * P], q[64 * P], rd[64 * P], ro[64 * P], rr[64 * P];
-  __shared__ int grp[64 * P];
-  __shared__ unsigned char stt[64 * P];
-  __shared__ int res_sh;
-  const int lane = threadIdx.x;
-  const int NF = a.M + 1;
-  for (int h = blockIdx.x; h < nhard; h += gridDim.x) {
-    const int line = hard_list[h];
-    const size_t base = (size_t)line * NF;
-    for (int t = lane; t < 64 * P; t += 64) {
-      sIp[lds_pad(t)] = (t < a.M) ? a.Ip[(size_t)line * a.M + t] : 0.0f;
-      sIm[lds_pad(t)] = (t < a.M) ? a.Im[(size_t)line * a.M + t] : 0.0f;
-    }
-    float b[P], z[P], u[P];
-    stage_in<P>(bvec + base, NF, true, stg, b, lane);
-    stage_in<P>(zvec + base, NF, true, stg, z, lane);
-    stage_in<P>(uvec + base, NF, true, stg, u, lane);
-    float Gdr[P], Gor[P], cr[P], gr[P];
-    qp_data<P>(a, (float)st->rho, b, z, u, sIp, sIm, lane, Gdr, Gor, cr, gr);
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int i = P * lane + j;
-      Gd[i] = Gdr[j];
-      Go[i] = Gor[j];
-      cv[i] = cr[j];
-      g0[i] = gr[j];
-    }
-    __syncthreads();
-    if (lane == 0)
-      res_sh = active_set_serial(NF, a.hp, Gd, Go, cv, g0, x, p, o, q, rd, ro, rr, grp, stt,
-                                 4 * NF);
-    __syncthreads();
-    float bn[P], wn[P];
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int i = P * lane + j;
-      bn[j] = (i < NF) ? b[j] + x[i] : 0.0f;
-      wn[j] = bn[j] + u[j];
-    }
-    stage_out<P>(bvec + base, NF, true, stg, bn, lane);
-    stage_out<P>(wvec + base, NF, true, stg, wn, lane);
-    if (lane == 0) atomicMax(&st->max_active, res_sh & 0xffff);
-    __syncthreads();
-  }
+  if ((int)blockIdx.x >= nhard) return;
+  __shared__ HardLds<P> L;
+  for (int h = blockIdx.x; h < nhard; h += gridDim.x)
+    hard_line_body<P>(a, (float)st->rho, bvec, zvec, uvec, wvec, hard_list[h], L, threadIdx.x,
+                      &st->max_active);
 }
 
 // ------------------------------------------------------------------------------------

@@ -80,6 +80,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1607_00531_amd.build")
+        # torch's HIP runtime is loaded first so that libepi.so binds to that same runtime
+        # (a second copy of libamdhip64 in the process sees no device).
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, st = C.c_void_p, C.c_int
         L.epi_abi_version.restype = C.c_int32
@@ -281,3 +284,128 @@ class Problem:
             out["kernel_ms"] = {n: prof.ms[i] for i, n in enumerate(KERNEL_NAMES)}
             out["kernel_launches"] = {n: int(prof.launches[i]) for i, n in enumerate(KERNEL_NAMES)}
         return out
+
+
+EPI_EBUSY = 7
+STATUS_NAMES[EPI_EBUSY] = "EPI_EBUSY"
+
+
+def _batch_sigs(L):
+    vp = C.c_void_p
+    if getattr(L, "_batch_sigs", False):
+        return L
+    L.epi_batch_create.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int32, vp, C.POINTER(vp)]
+    L.epi_batch_create.restype = C.c_int
+    L.epi_batch_footprint.argtypes = [C.POINTER(Grid), C.c_int32]
+    L.epi_batch_footprint.restype = C.c_int64
+    L.epi_batch_admit.argtypes = [vp, C.POINTER(Grid), vp, vp, vp, vp, vp, C.POINTER(ADMMOpts),
+                                  C.POINTER(C.c_int32)]
+    L.epi_batch_admit.restype = C.c_int
+    L.epi_batch_step.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.epi_batch_step.restype = C.c_int
+    L.epi_batch_poll.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(ADMMReport)]
+    L.epi_batch_poll.restype = C.c_int
+    L.epi_batch_release.argtypes = [vp, C.c_int32]
+    L.epi_batch_release.restype = C.c_int
+    L.epi_batch_destroy.argtypes = [vp]
+    L.epi_batch_destroy.restype = None
+    L._batch_sigs = True
+    return L
+
+
+def _grid_struct(shape_cells, h, alpha, beta, gamma, precision, ndim=None):
+    m3, m2, M = (int(s) for s in shape_cells)
+    g = Grid()
+    g.ndim = ndim if ndim is not None else (2 if m3 == 1 else 3)
+    g.m[0], g.m[1], g.m[2] = M, m2, m3
+    for a in range(3):
+        g.h[a] = float(h[a])
+    g.alpha, g.beta, g.gamma = float(alpha), float(beta), float(gamma)
+    g.precision = PREC[precision]
+    return g
+
+
+class Batch:
+    """Continuous-batching ADMM engine (epi_batch_*): admit volumes of different sizes, step
+    all running ones together, poll and release finished ones. Tensors handed to `admit`
+    are kept referenced until the slot is released."""
+
+    def __init__(self, max_slots: int = 16, hbm_budget_bytes: int = 64 << 30,
+                 precision: str = "mixed", iters_per_step: int = 8, stream=None):
+        L = _batch_sigs(lib())
+        self._h = C.c_void_p()
+        self.precision = precision
+        _check(L.epi_batch_create(int(max_slots), int(hbm_budget_bytes), PREC[precision],
+                                  int(iters_per_step), _stream_handle(stream), C.byref(self._h)))
+        self._keep = {}
+        self._maxit = {}
+
+    @staticmethod
+    def footprint(shape_cells, h, alpha=50.0, max_iter=2000) -> int:
+        g = _grid_struct(shape_cells, h, alpha, 10.0, 1e-3, "mixed")
+        return int(_batch_sigs(lib()).epi_batch_footprint(C.byref(g), int(max_iter)))
+
+    def admit(self, Ip, Im, h, alpha, b, z, u, beta=10.0, gamma=1e-3, ndim=None, **opts):
+        """Returns the slot index, or None when the engine is busy (EPI_EBUSY)."""
+        L = _batch_sigs(lib())
+        g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, self.precision, ndim)
+        o = ADMMOpts()
+        L.epi_admm_default_opts(C.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        slot = C.c_int32(-1)
+        st = L.epi_batch_admit(self._h, C.byref(g), _ptr(Ip), _ptr(Im), _ptr(b), _ptr(z),
+                               _ptr(u), C.byref(o), C.byref(slot))
+        if st == EPI_EBUSY:
+            return None
+        _check(st)
+        self._keep[slot.value] = (Ip, Im, b, z, u)
+        self._maxit[slot.value] = max(o.max_iter, 1)
+        return slot.value
+
+    def step(self) -> int:
+        n = C.c_int32(0)
+        _check(_batch_sigs(lib()).epi_batch_step(self._h, C.byref(n)))
+        return n.value
+
+    def poll(self, slot: int):
+        """None while running, else the report dict (as Problem.solve_admm returns)."""
+        L = _batch_sigs(lib())
+        fin = C.c_int32(0)
+        n1 = self._maxit[slot]
+        arrs = {k: (C.c_double * n1)() for k in ("r_pri", "r_dual", "eps_pri", "eps_dual")}
+        rep = ADMMReport()
+        for k, a in arrs.items():
+            setattr(rep, k, C.cast(a, C.POINTER(C.c_double)))
+        _check(L.epi_batch_poll(self._h, int(slot), C.byref(fin), C.byref(rep)))
+        if not fin.value:
+            return None
+        k = rep.iters
+        out = dict(iters=k, converged=bool(rep.converged), max_active=rep.max_active,
+                   hard_lines=int(rep.hard_lines))
+        for key, a in arrs.items():
+            out[key] = list(a[:k])
+        return out
+
+    def release(self, slot: int):
+        _check(_batch_sigs(lib()).epi_batch_release(self._h, int(slot)))
+        self._keep.pop(slot, None)
+        self._maxit.pop(slot, None)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _batch_sigs(lib()).epi_batch_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,153 @@
+"""The continuous-batching ADMM engine (epi_batch_*) on the GPU: each volume's result is the
+same alone and in a mixed batch, equals the single-volume solver and the oracle within the
+stated tolerances, admission respects slots and the HBM budget, and freed slots are reused."""
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import generate
+from tests.gpu_common import T, N, FIELD_VOX
+
+pytestmark = pytest.mark.gpu
+
+# mixed sizes: 2D and 3D, 1..4 faces per lane, both DCT tile classes (<= 128 and > 128 rows)
+MIX = [((40, 36), 1, 0.5), ((24, 20, 14), 0, 5.0), ((70, 30, 12), 1, 2.0), ((200, 18, 9), 0, 50.0),
+       ((20, 150, 6), 1, 5.0), ((48, 44), 0, 50.0)]
+
+
+def _vols():
+    return [(generate(10 + i, m, pe), a) for i, (m, pe, a) in enumerate(MIX)]
+
+
+def _state(v):
+    M, m2, m3 = v.m
+    return [T(np.zeros((m3, m2, M + 1))) for _ in range(3)]
+
+
+def _run_batch(items, prec="mixed", iters_per_step=4, max_slots=16, **opts):
+    from paper_1607_00531_amd import Batch
+    out = {}
+    with Batch(max_slots=max_slots, precision=prec, iters_per_step=iters_per_step) as bt:
+        slots = {}
+        for key, (v, alpha) in items:
+            st = _state(v)
+            s = bt.admit(T(v.Ip), T(v.Im), v.h, alpha, *st, **opts)
+            assert s is not None
+            slots[s] = (key, st)
+        while bt.step() > 0:
+            pass
+        for s, (key, st) in slots.items():
+            rep = bt.poll(s)
+            assert rep is not None
+            out[key] = (rep, [N(x) for x in st])
+            bt.release(s)
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_result_is_the_same_alone_and_in_the_mix(prec):
+    vols = _vols()
+    opts = dict(rho=1e3, max_iter=24, eps_abs=0.0, eps_rel=2e-3)
+    mix = _run_batch(list(enumerate(vols)), prec, **opts)
+    for i, item in enumerate(vols):
+        alone = _run_batch([(i, item)], prec, **opts)[i]
+        assert alone[0]["iters"] == mix[i][0]["iters"]
+        assert alone[0]["converged"] == mix[i][0]["converged"]
+        for a, b in zip(alone[1], mix[i][1]):
+            np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(alone[0]["r_pri"], mix[i][0]["r_pri"])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_batch_matches_single_volume_solver_and_oracle(prec):
+    """The batch kernels tile the DCT with one tile class for every volume, the single-volume
+    solver picks it by size, so the two agree to rounding (1e-4 voxel), not bitwise. The
+    oracle bar (1e-3 voxel after 15 iterations) is checked in float32; the split-bfloat16
+    transform's rounding against the oracle is covered by the single-volume trajectories."""
+    from paper_1607_00531_amd import Problem
+    vols = _vols()
+    opts = dict(rho=1e3, max_iter=15, eps_abs=0.0, eps_rel=0.0)
+    mix = _run_batch(list(enumerate(vols)), prec, iters_per_step=5, **opts)
+    for i, (v, alpha) in enumerate(vols):
+        with Problem(T(v.Ip), T(v.Im), v.h, alpha, precision=prec) as pr:
+            st = _state(v)
+            rep = pr.solve_admm(*st, **opts)
+        assert rep["iters"] == mix[i][0]["iters"] == 15
+        for a, b in zip(mix[i][1], st):
+            assert np.abs(a - N(b)).max() / v.h[0] <= 1e-4
+        if prec == "fp32" and i < 3:
+            P = O.make_problem(v.Ip, v.Im, v.h, alpha)
+            bo, zo, uo, _ = O.solve_admm(P, rho=1e3, max_iter=15, eps_abs=0.0, eps_rel=0.0)
+            for a, c in zip(mix[i][1], (bo, zo, uo)):
+                assert np.abs(a - c).max() / v.h[0] <= FIELD_VOX
+
+
+def test_admission_budget_busy_and_slot_reuse():
+    from paper_1607_00531_amd import Batch
+    v, alpha = _vols()[1]
+    fp = Batch.footprint(v.Ip.shape, v.h, alpha, max_iter=40)
+    assert fp > 4 * (2 * v.Ip.size + 3 * v.b_true.size)
+    with Batch(max_slots=4, hbm_budget_bytes=int(2.5 * fp), precision="mixed",
+               iters_per_step=4) as bt:
+        st = [_state(v) for _ in range(3)]
+        s0 = bt.admit(T(v.Ip), T(v.Im), v.h, alpha, *st[0], rho=1e3, max_iter=40, eps_abs=0.0, eps_rel=1e-3)
+        s1 = bt.admit(T(v.Ip), T(v.Im), v.h, alpha, *st[1], rho=1e3, max_iter=8, eps_abs=0.0, eps_rel=0.0)
+        assert s0 is not None and s1 is not None and s0 != s1
+        # a third request does not fit the budget until a slot is released
+        assert bt.admit(T(v.Ip), T(v.Im), v.h, alpha, *st[2], rho=1e3, max_iter=40, eps_abs=0.0, eps_rel=1e-3) is None
+        while bt.poll(s1) is None:
+            bt.step()
+        assert bt.poll(s1)["iters"] == 8
+        bt.release(s1)
+        s2 = bt.admit(T(v.Ip), T(v.Im), v.h, alpha, *st[2], rho=1e3, max_iter=40, eps_abs=0.0, eps_rel=1e-3)
+        assert s2 == s1       # the freed slot is reused while s0 keeps running
+        while bt.step() > 0:
+            pass
+        r0, r2 = bt.poll(s0), bt.poll(s2)
+        assert r0["iters"] == r2["iters"]
+        for a, b in zip(st[0], st[2]):
+            np.testing.assert_array_equal(N(a), N(b))
+
+
+def test_batch_rejects_bad_requests():
+    from paper_1607_00531_amd import Batch, EpiError, EPI_EINFEASIBLE, EPI_EINVAL
+    v, alpha = _vols()[0]
+    M, m2, m3 = v.m
+    bad = np.zeros((m3, m2, M + 1))
+    bad[..., 5:] += 1.5 * v.h[0]
+    with Batch(max_slots=2, precision="fp32") as bt:
+        with pytest.raises(EpiError) as e:
+            bt.admit(T(v.Ip), T(v.Im), v.h, alpha, T(bad), T(bad), T(np.zeros_like(bad)), rho=1e3, max_iter=5)
+        assert e.value.status == EPI_EINFEASIBLE
+        with pytest.raises(EpiError) as e:
+            bt.admit(T(v.Ip), T(v.Im), v.h, alpha, *_state(v), rho=0.0, max_iter=5)
+        assert e.value.status == EPI_EINVAL
+        assert bt.step() == 0
+
+
+def test_active_set_lines_in_a_batch():
+    r = np.random.default_rng(17)
+    M, m2, m3 = 12, 6, 4
+    Ip = 3.0 * r.uniform(0.2, 1.0, size=(m3, m2, M))
+    Im = 3.0 * r.uniform(0.2, 1.0, size=(m3, m2, M))
+    h = (1 / M, 1 / m2, 1 / m3)
+    P = O.make_problem(Ip, Im, h, 0.02)
+    g = np.cumsum(r.normal(size=(P.L, P.M + 1)), axis=1)
+    g *= 0.7 / np.abs(np.diff(g, axis=1) / P.hp).max()
+    b0 = g
+    z0 = b0 + 0.3 * P.hp * r.normal(size=b0.shape)
+    u0 = 0.1 * P.hp * r.normal(size=b0.shape)
+    bn, nact, _ = O.bstep(P, b0, z0, u0, 50.0)
+    zn = O.zstep(P, bn + u0, 50.0)
+    un = u0 + bn - zn
+    from paper_1607_00531_amd import Batch
+    sh = (m3, m2, M + 1)
+    with Batch(max_slots=2, precision="fp32", iters_per_step=1) as bt:
+        st = [T(x.reshape(sh)) for x in (b0, z0, u0)]
+        s = bt.admit(T(Ip), T(Im), h, 0.02, *st, rho=50.0, max_iter=1, eps_abs=0.0, eps_rel=0.0)
+        while bt.step() > 0:
+            pass
+        rep = bt.poll(s)
+        assert rep["hard_lines"] > 0 and rep["max_active"] == int(nact.max())
+        for gpu, cpu in zip(st, (bn, zn, un)):
+            assert np.abs(N(gpu).reshape(P.L, -1) - cpu).max() / P.hp <= FIELD_VOX
