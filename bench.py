@@ -7,7 +7,18 @@ unknowns), alpha = 50, rho = 1e3, solved from b = z = u = 0 to the relative resi
 One step = one volume solved to that tolerance. The mixed-precision solver (split-bf16
 MFMA DCT) gives `value`; the plain float32 solver is timed beside it. Inputs are resident in
 HBM and the problem handles exist before the timed region (slot preallocation); each step
-clears the state and runs the whole solve. Prints one JSON line on stdout.
+clears the state and runs the whole solve.
+
+Two more legs time the continuous-batching engine (epi_batch_*) against the plain float32
+single-volume solver:
+  * batched: 48 volumes, each axis uniform in [96,160] x [96,160] x [48,96], PE axis drawn
+    per volume, 40 ADMM iterations each, admitted together (setup inside the timed region);
+  * served: a Poisson request stream (20 req/s; 30% 2D slices 128..256 per side, 70% 3D
+    volumes 64..240 x 64..200 x 64..110), each request solved from zero to the relative
+    residual 1e-3; latency = completion - arrival. Requests draw their images from a pool
+    of volumes generated from the stream's first requests (generation is far slower than
+    the arrival rate), uploaded to HBM before the stream starts.
+Prints one JSON line on stdout.
 """
 from __future__ import annotations
 
@@ -106,6 +117,213 @@ def cpu_baseline(vol, gpu_iters_mean, iters):
                       f"BLAS threads {blas}"}
 
 
+def engine_same_volumes(imgs, vols, m3, m2, M, steps, max_iter, iters_per_step=16):
+    """The batching engine (mixed precision) on the headline volumes: all of them admitted
+    together, each solved from zero to the relative residual 1e-3; `steps` volumes in
+    total after one warm-up round. Admission is inside the timed region."""
+    import torch
+    from paper_1607_00531_amd import Batch
+    dev = imgs[0][0].device
+    states = [[torch.zeros((m3, m2, M + 1), device=dev) for _ in range(3)] for _ in imgs]
+    opts = dict(rho=RHO, max_iter=max_iter, eps_abs=0.0, eps_rel=TOL)
+
+    def one_round(bt, k):
+        for st in states[:k]:
+            for t in st:
+                t.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        slots = [bt.admit(Ip, Im, v.h, ALPHA, *st, beta=BETA, **opts)
+                 for (Ip, Im), v, st in zip(imgs[:k], vols[:k], states[:k])]
+        while bt.step() > 0:
+            pass
+        reps = [bt.poll(x) for x in slots]
+        for x in slots:
+            bt.release(x)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, reps
+
+    with Batch(max_slots=len(imgs), precision="mixed", iters_per_step=iters_per_step) as bt:
+        one_round(bt, len(imgs))
+        done, total, iters, conv = 0, 0.0, [], []
+        while done < steps:
+            k = min(len(imgs), steps - done)
+            dt, reps = one_round(bt, k)
+            total += dt
+            done += k
+            iters += [r["iters"] for r in reps]
+            conv += [r["converged"] for r in reps]
+    return {"value": round(done / total, 3), "unit": "volumes/s", "volumes": done,
+            "resident": len(imgs), "iters": iters, "converged": all(conv),
+            "iters_per_step": iters_per_step}
+
+
+def batched_leg(dev, n_vol, iters, log_every=8):
+    """48 uneven volumes, a fixed number of ADMM iterations each: the batching engine in
+    mixed precision (all admitted together) against the float32 and mixed single-volume
+    solvers one after another. Setup (admission / problem creation) is timed in all three."""
+    import torch
+    from synth import generate, batch_shapes
+    from paper_1607_00531_amd import Batch, Problem
+
+    items = []
+    t0 = time.perf_counter()
+    for s, m, pe in batch_shapes(n_vol):
+        v = generate(s, m, pe)
+        items.append((v, torch.tensor(v.Ip, dtype=torch.float32, device=dev),
+                      torch.tensor(v.Im, dtype=torch.float32, device=dev)))
+        if (s + 1) % log_every == 0:
+            log(f"batched leg: generated {s + 1}/{n_vol} volumes ({time.perf_counter() - t0:.0f} s)")
+    faces = sum((v.m[0] + 1) * v.m[1] * v.m[2] for v, _, _ in items)
+    states = [[torch.zeros((v.m[2], v.m[1], v.m[0] + 1), device=dev) for _ in range(3)]
+              for v, _, _ in items]
+    opts = dict(rho=RHO, max_iter=iters, eps_abs=0.0, eps_rel=0.0)
+
+    def clear():
+        for st in states:
+            for t in st:
+                t.zero_()
+        torch.cuda.synchronize()
+
+    def run_batch(iters_per_step):
+        clear()
+        t0 = time.perf_counter()
+        with Batch(max_slots=n_vol, precision="mixed", iters_per_step=iters_per_step) as bt:
+            slots = [bt.admit(Ip, Im, v.h, ALPHA, *st, beta=BETA, **opts)
+                     for (v, Ip, Im), st in zip(items, states)]
+            if any(x is None for x in slots):
+                raise RuntimeError("batched leg: admission refused")
+            while bt.step() > 0:
+                pass
+            reps = [bt.poll(x) for x in slots]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        assert all(r is not None and r["iters"] == iters for r in reps)
+        return dt
+
+    def run_single(precision):
+        clear()
+        t0 = time.perf_counter()
+        for (v, Ip, Im), st in zip(items, states):
+            with Problem(Ip, Im, v.h, ALPHA, BETA, precision=precision) as pr:
+                r = pr.solve_admm(*st, check_every=iters, **opts)
+                assert r["iters"] == iters
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    run_batch(8)                       # warm-up (code objects, graph instantiation)
+    run_single("fp32")
+    t_batch = run_batch(8)
+    log(f"batched leg: engine {n_vol / t_batch:.2f} volumes/s")
+    t_fp32 = run_single("fp32")
+    log(f"batched leg: plain fp32 {n_vol / t_fp32:.2f} volumes/s")
+    t_mixed = run_single("mixed")
+    log(f"batched leg: single-volume mixed {n_vol / t_mixed:.2f} volumes/s")
+    return {"workload": f"{n_vol} volumes, axes uniform in [96,160]x[96,160]x[48,96], PE axis "
+                        f"per volume, {iters} ADMM iterations each, alpha=50 rho=1e3",
+            "faces_total": faces,
+            "engine_mixed": {"value": round(n_vol / t_batch, 3), "unit": "volumes/s",
+                             "s_total": round(t_batch, 4)},
+            "plain_fp32": {"value": round(n_vol / t_fp32, 3), "unit": "volumes/s",
+                           "s_total": round(t_fp32, 4)},
+            "single_volume_mixed": {"value": round(n_vol / t_mixed, 3), "unit": "volumes/s",
+                                    "s_total": round(t_mixed, 4)},
+            "speedup_vs_plain_fp32": round(t_fp32 / t_batch, 3)}
+
+
+def served_leg(dev, seconds, rate, pool_size, max_iter):
+    """Open-loop Poisson stream served by the batching engine (mixed precision) and by the
+    plain float32 single-volume solver in arrival order; p50/p99 of completion - arrival."""
+    import torch
+    from synth import generate, serving_requests
+    from paper_1607_00531_amd import Batch, Problem
+
+    reqs = serving_requests(rate=rate, duration=seconds)
+    pool = []
+    t0 = time.perf_counter()
+    for t_a, q, m, pe in serving_requests(rate=rate, duration=max(seconds, 4.0 * pool_size / rate))[:pool_size]:
+        v = generate(q, m, pe)
+        pool.append((v, torch.tensor(v.Ip, dtype=torch.float32, device=dev),
+                     torch.tensor(v.Im, dtype=torch.float32, device=dev)))
+        if len(pool) % 8 == 0:
+            log(f"served leg: generated {len(pool)}/{pool_size} pool volumes "
+                f"({time.perf_counter() - t0:.0f} s)")
+    opts = dict(rho=RHO, max_iter=max_iter, eps_abs=0.0, eps_rel=TOL)
+
+    def fresh_state(v):
+        return [torch.zeros((v.m[2], v.m[1], v.m[0] + 1), device=dev) for _ in range(3)]
+
+    def serve_engine(stream, iters_per_step=8, max_slots=32):
+        pending = list(stream)             # (t_arrival, q)
+        pending.reverse()
+        waiting, lat, iters, conv = [], [], [], []
+        running = {}
+        with Batch(max_slots=max_slots, precision="mixed", iters_per_step=iters_per_step) as bt:
+            torch.cuda.synchronize()
+            start = time.perf_counter()
+            while pending or waiting or running:
+                now = time.perf_counter() - start
+                while pending and pending[-1][0] <= now:
+                    waiting.append(pending.pop())
+                while waiting:
+                    t_a, q = waiting[0]
+                    v, Ip, Im = pool[q % len(pool)]
+                    st = fresh_state(v)
+                    slot = bt.admit(Ip, Im, v.h, ALPHA, *st, beta=BETA, **opts)
+                    if slot is None:
+                        break
+                    waiting.pop(0)
+                    running[slot] = t_a
+                if running:
+                    bt.step()
+                    for slot in list(running):
+                        r = bt.poll(slot)
+                        if r is not None:
+                            lat.append(time.perf_counter() - start - running.pop(slot))
+                            iters.append(r["iters"])
+                            conv.append(r["converged"])
+                            bt.release(slot)
+                elif pending:
+                    time.sleep(max(0.0, min(pending[-1][0] - now, 0.005)))
+            total = time.perf_counter() - start
+        return lat, iters, conv, total
+
+    def serve_single(stream, precision="fp32"):
+        lat, iters, conv = [], [], []
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        for t_a, q in stream:
+            now = time.perf_counter() - start
+            if now < t_a:
+                time.sleep(t_a - now)
+            v, Ip, Im = pool[q % len(pool)]
+            st = fresh_state(v)
+            with Problem(Ip, Im, v.h, ALPHA, BETA, precision=precision) as pr:
+                r = pr.solve_admm(*st, check_every=16, **opts)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - start - t_a)
+            iters.append(r["iters"])
+            conv.append(r["converged"])
+        return lat, iters, conv, time.perf_counter() - start
+
+    stream = [(t, q) for t, q, _, _ in reqs]
+    serve_engine(stream[:min(8, len(stream))])      # warm-up
+    out = {"workload": f"Poisson stream {rate:g} req/s for {seconds:g} s ({len(stream)} "
+                       f"requests), 30% 2D 128..256^2, 70% 3D 64..240x64..200x64..110, "
+                       f"images from a pool of {len(pool)} generated requests, solve to "
+                       f"rel. residual 1e-3 from zero",
+           "requests": len(stream)}
+    for name, fn in (("engine_mixed", serve_engine), ("plain_fp32", serve_single)):
+        lat, iters, conv, total = fn(stream)
+        out[name] = {"volumes_per_s": round(len(lat) / total, 3),
+                     "p50_ms": round(1e3 * percentile(lat, 50), 2),
+                     "p99_ms": round(1e3 * percentile(lat, 99), 2),
+                     "completed": len(lat), "converged": int(sum(conv)),
+                     "mean_iters": round(float(np.mean(iters)), 1), "s_total": round(total, 3)}
+        log(f"served leg: {name} {json.dumps(out[name])}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +336,13 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--max-iter", type=int, default=MAX_ITER,
                     help="ADMM iteration cap per solve (short profiling runs)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 48-volume batched leg")
+    ap.add_argument("--batch-volumes", type=int, default=48)
+    ap.add_argument("--batch-iters", type=int, default=40)
+    ap.add_argument("--no-served", action="store_true", help="skip the request-stream leg")
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 512 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -184,6 +409,12 @@ def main():
     value = args.steps / total
     log(f"mixed: {value:.2f} volumes/s, iterations {iters}, converged {conv}")
 
+    engine = None
+    if not args.no_served:
+        log("timing the batching engine on the same volumes (all resident together)")
+        engine = engine_same_volumes(imgs, vols, m3, m2, M, args.steps, args.max_iter)
+        log(f"engine: {json.dumps(engine)}")
+
     # per-kernel device time of one profiled solve (HIP events on the library stream)
     for t in state:
         t.zero_()
@@ -233,6 +464,16 @@ def main():
               "pcg_iters": r["pcg_iters"], "converged": r["converged"],
               "stop": "|grad J_GN| <= 1e-3 |grad J_GN(0)| or 30 GN steps"}
 
+    batched = None
+    if not args.no_batched:
+        log("batched leg")
+        batched = batched_leg(dev, args.batch_volumes, args.batch_iters)
+
+    served = None
+    if not args.no_served:
+        log("served leg")
+        served = served_leg(dev, args.serve_seconds, args.serve_rate, args.serve_pool, MAX_ITER)
+
     base = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
@@ -264,7 +505,10 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "plain_fp32": plain,
+        "engine_same_volumes": engine,
         "gnpcg": gn,
+        "batched": batched,
+        "served": served,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

@@ -29,9 +29,7 @@
 
 namespace epi {
 
-#define BATCH_LINE_GRID 2048
 #define BATCH_HARD_GRID 128
-#define BATCH_DCT_GRID 1024
 
 // index k of the range holding item i: first[k] <= i < first[k+1]
 __device__ __forceinline__ int range_find(const RangeTable& T, int i) {
@@ -47,26 +45,27 @@ __device__ __forceinline__ int range_find(const RangeTable& T, int i) {
 template <int P>
 __global__ __launch_bounds__(256) void k_batch_bstep(BatchDev* bd, int cls) {
   const RangeTable& T = bd->bt[cls];
-  if (T.n == 0) return;
-  const int total = T.first[T.n];
-  const int units = (total + EPI_LINE_WAVES - 1) / EPI_LINE_WAVES;
+  const int nr = T.n;
+  if (nr == 0) return;
+  const int total = T.first[nr];
   __shared__ float sbuf[EPI_LINE_WAVES][5][LineBuf<P>::SIZE];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int unit = blockIdx.x; unit < units; unit += gridDim.x) {
-    const int gl = unit * EPI_LINE_WAVES + wave;
-    const int k = range_find(T, gl < total ? gl : total - 1);
-    const int slot = T.slot[k];
-    const BatchSlotDev& S = bd->slots[slot];
-    const bool valid = gl < total && !S.st->admm_done;
-    const int line = gl < total ? gl - T.first[k] : 0;
-    const bool hard = bstep_line_body<P>(S.la, (float)S.st->rho, S.b, S.z, S.u, S.w,
-                                         valid ? line : 0, valid, &sbuf[wave][0][0], lane,
-                                         &S.st->numeric_bad);
-    if (valid && hard && lane == 0) {
-      const int idx = atomicAdd(&bd->hard_count[cls], 1);
-      bd->hard_list[cls][idx] = HardItem{slot, line};
-      atomicAdd(&S.st->hard_count, 1);
-    }
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int unit = xcd_remap(blockIdx.x, gridDim.x);
+  const int gl = unit * EPI_LINE_WAVES + wave;
+  if (gl >= total) return;
+  const int k = range_find(T, gl);
+  const int slot = T.slot[k];
+  const BatchSlotDev& S = bd->slots[slot];
+  DevState* st = S.st;
+  if (st->admm_done) return;
+  const int line = gl - T.first[k];
+  const bool hard = bstep_line_body<P>(S.la, (float)st->rho, S.b, S.z, S.u, S.w, line, true,
+                                       &sbuf[wave][0][0], lane, &st->numeric_bad);
+  if (hard && lane == 0) {
+    const int idx = atomicAdd(&bd->hard_count[cls], 1);
+    bd->hard_list[cls][idx] = HardItem{slot, line};
+    atomicAdd(&st->hard_count, 1);
   }
 }
 
@@ -86,24 +85,25 @@ __global__ __launch_bounds__(64) void k_batch_hard(BatchDev* bd, int cls) {
 template <int PREC, bool FUSED, int EPI, int KSM, int SLOTS>
 __global__ __launch_bounds__(256) void k_batch_dct(BatchDev* bd, int cls, int pass) {
   const RangeTable& T = bd->dt[cls];
-  if (T.n == 0) return;
-  const int total = T.first[T.n];
+  const int nr = T.n;
+  if (nr == 0) return;
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  if (t >= T.first[nr]) return;
+  const int k = range_find(T, t);
+  const BatchSlotDev& S = bd->slots[T.slot[k]];
+  if (S.st->admm_done) return;
+  // a copy: the body reads its fields between global stores
+  const GemmArgs g = pass == 1 ? S.g1 : (pass == 2 ? S.g2 : S.g3);
+  const int local = t - T.first[k];
+  const int batch = local / g.col_tiles;
+  const int c0 = (local % g.col_tiles) * DCT_NT;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    const int k = range_find(T, t);
-    const BatchSlotDev& S = bd->slots[T.slot[k]];
-    if (S.st->admm_done) continue;
-    const GemmArgs& g = pass == 1 ? S.g1 : (pass == 2 ? S.g2 : S.g3);
-    const int local = t - T.first[k];
-    const int batch = local / g.col_tiles;
-    const int c0 = (local % g.col_tiles) * DCT_NT;
-    if (PREC == 1)
-      dct_bf16_body<FUSED, EPI, KSM, SLOTS>(g, batch, c0, local,
-                                            reinterpret_cast<unsigned short*>(lds_raw));
-    else
-      dct_f32_body<FUSED, EPI, KSM * 8, SLOTS>(g, batch, c0, local,
-                                               reinterpret_cast<float*>(lds_raw));
-  }
+  if (PREC == 1)
+    dct_bf16_body<FUSED, EPI, KSM, SLOTS>(g, batch, c0, local,
+                                          reinterpret_cast<unsigned short*>(lds_raw));
+  else
+    dct_f32_body<FUSED, EPI, KSM * 8, SLOTS>(g, batch, c0, local,
+                                             reinterpret_cast<float*>(lds_raw));
 }
 
 // one workgroup per slot: float64 reduction of the last pass's sums and the stopping test
@@ -127,16 +127,28 @@ static size_t dct_class_lds(int prec, bool small) {
 }
 
 template <bool FUSED, int EPI>
-static void launch_batch_dct(hipStream_t s, int prec, BatchDev* bd, int cls, int pass, bool small) {
+static void launch_batch_dct(hipStream_t s, int prec, BatchDev* bd, int cls, int pass, bool small,
+                             int grid) {
   const size_t lds = dct_class_lds(prec, small);
-  const dim3 grid(BATCH_DCT_GRID), blk(256);
+  const dim3 g(grid), blk(256);
   if (prec == 1) {
-    if (small) hipLaunchKernelGGL((k_batch_dct<1, FUSED, EPI, 4, 2>), grid, blk, lds, s, bd, cls, pass);
-    else hipLaunchKernelGGL((k_batch_dct<1, FUSED, EPI, 8, 4>), grid, blk, lds, s, bd, cls, pass);
+    if (small) hipLaunchKernelGGL((k_batch_dct<1, FUSED, EPI, 4, 2>), g, blk, lds, s, bd, cls, pass);
+    else hipLaunchKernelGGL((k_batch_dct<1, FUSED, EPI, 8, 4>), g, blk, lds, s, bd, cls, pass);
   } else {
-    if (small) hipLaunchKernelGGL((k_batch_dct<0, FUSED, EPI, 4, 2>), grid, blk, lds, s, bd, cls, pass);
-    else hipLaunchKernelGGL((k_batch_dct<0, FUSED, EPI, 8, 4>), grid, blk, lds, s, bd, cls, pass);
+    if (small) hipLaunchKernelGGL((k_batch_dct<0, FUSED, EPI, 4, 2>), g, blk, lds, s, bd, cls, pass);
+    else hipLaunchKernelGGL((k_batch_dct<0, FUSED, EPI, 8, 4>), g, blk, lds, s, bd, cls, pass);
   }
+}
+
+// Launch width for n work units: n rounded up to 8..15 times a power of two, so that the
+// captured graph (whose launch widths are fixed) is captured again only when the work
+// of a class moves to another bucket; the spare workgroups return at once (< 1/8).
+static int bucket_grid(long long n) {
+  if (n <= 16) return (int)(n < 1 ? 1 : n);
+  int e = 0;
+  while ((n >> e) >= 16) ++e;
+  const long long step = 1LL << e;
+  return (int)(((n + step - 1) / step) * step);
 }
 
 template <bool FUSED, int EPI>
@@ -189,6 +201,16 @@ int64_t workspace_bytes(const epi_grid* g, int max_iter) {
 
 }  // namespace
 
+// Launch widths of every kernel class of one captured iteration (0: class absent).
+struct BatchKey {
+  int bstep[EPI_PMAX + 1] = {0};
+  int dct[8] = {0};
+  bool operator==(const BatchKey& o) const {
+    return memcmp(bstep, o.bstep, sizeof(bstep)) == 0 && memcmp(dct, o.dct, sizeof(dct)) == 0;
+  }
+  bool operator!=(const BatchKey& o) const { return !(*this == o); }
+};
+
 struct epi_batch {
   int max_slots = 0, precision = 1, iters_per_step = 8;
   int64_t budget = 0, used_bytes = 0;
@@ -204,7 +226,7 @@ struct epi_batch {
   bool dirty = true;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  uint32_t graph_key = 0xffffffffu;
+  BatchKey graph_key;
   int running = 0;
 };
 
@@ -393,12 +415,11 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
   return EPI_OK;
 }
 
-// work tables of the running volumes, uploaded to the device; returns the class key
-static epi_status batch_rebuild(epi_batch* bt, uint32_t* key) {
+// work tables of the running volumes, uploaded to the device; returns the launch widths
+static epi_status batch_rebuild(epi_batch* bt, BatchKey* key) {
   BatchDev* h = bt->h_bd;
   memset(h, 0, sizeof(BatchDev));
   int need[EPI_PMAX + 1] = {0};
-  uint32_t k = 0;
   bt->running = 0;
   for (int i = 0; i < bt->max_slots; ++i) {
     SlotHost& s = bt->slots[i];
@@ -424,7 +445,6 @@ static epi_status batch_rebuild(epi_batch* bt, uint32_t* key) {
     };
     add(h->bt[s.P], s.L);
     need[s.P] += s.L;
-    k |= 1u << s.P;
     const int small3 = s.m3 <= 128 ? 0 : 1, small2 = s.m2 <= 128 ? 0 : 1;
     if (three) {
       d.g1 = make_gemm_axis3(s.M, s.m2, s.m3, alpha, s.tab, s.w, s.t1, false, d.st);
@@ -440,9 +460,6 @@ static epi_status batch_rebuild(epi_batch* bt, uint32_t* key) {
       add(h->dt[0 + small3], d.g1.nbatch * d.g1.col_tiles);
       add(h->dt[2 + small2], d.g2.nbatch * d.g2.col_tiles);
       add(h->dt[6 + small3], d.g3.nbatch * d.g3.col_tiles);
-      k |= 1u << (16 + small3);
-      k |= 1u << (16 + 2 + small2);
-      k |= 1u << (16 + 6 + small3);
     } else {
       d.g2 = make_gemm_axis2(s.M, s.m2, s.m3, alpha, s.tab, s.w, s.z, d.st);
       d.g2.epi = 1;
@@ -453,7 +470,6 @@ static epi_status batch_rebuild(epi_batch* bt, uint32_t* key) {
       d.last_ntiles = d.g2.nbatch * d.g2.col_tiles;
       d.last_partial = s.partial;
       add(h->dt[4 + small2], d.g2.nbatch * d.g2.col_tiles);
-      k |= 1u << (16 + 4 + small2);
     }
   }
   for (int c = 1; c <= EPI_PMAX; ++c) {
@@ -466,28 +482,34 @@ static epi_status batch_rebuild(epi_batch* bt, uint32_t* key) {
     h->hard_list[c] = bt->hard[c];
   }
   BHIPCHK(hipMemcpyAsync(bt->d_bd, h, sizeof(BatchDev), hipMemcpyHostToDevice, bt->exec));
+  BatchKey k;
+  for (int c = 1; c <= EPI_PMAX; ++c)   // one workgroup per EPI_LINE_WAVES lines
+    if (h->bt[c].n) k.bstep[c] = bucket_grid((h->bt[c].first[h->bt[c].n] + EPI_LINE_WAVES - 1) / EPI_LINE_WAVES);
+  for (int c = 0; c < 8; ++c)           // one workgroup per 64-column tile
+    if (h->dt[c].n) k.dct[c] = bucket_grid(h->dt[c].first[h->dt[c].n]);
   *key = k;
   return EPI_OK;
 }
 
-static void batch_iteration(epi_batch* bt, uint32_t key) {
+static void batch_iteration(epi_batch* bt, const BatchKey& key) {
   hipStream_t s = bt->exec;
   BatchDev* bd = bt->d_bd;
   for (int P = 1; P <= EPI_PMAX; ++P) {
-    if (!(key & (1u << P))) continue;
+    const dim3 g(key.bstep[P]), blk(256);
+    if (!key.bstep[P]) continue;
     switch (P) {
-      case 1: hipLaunchKernelGGL(k_batch_bstep<1>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
-      case 2: hipLaunchKernelGGL(k_batch_bstep<2>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
-      case 3: hipLaunchKernelGGL(k_batch_bstep<3>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
-      case 4: hipLaunchKernelGGL(k_batch_bstep<4>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
-      case 5: hipLaunchKernelGGL(k_batch_bstep<5>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
-      case 6: hipLaunchKernelGGL(k_batch_bstep<6>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
-      case 7: hipLaunchKernelGGL(k_batch_bstep<7>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
-      default: hipLaunchKernelGGL(k_batch_bstep<8>, dim3(BATCH_LINE_GRID), dim3(256), 0, s, bd, P); break;
+      case 1: hipLaunchKernelGGL(k_batch_bstep<1>, g, blk, 0, s, bd, P); break;
+      case 2: hipLaunchKernelGGL(k_batch_bstep<2>, g, blk, 0, s, bd, P); break;
+      case 3: hipLaunchKernelGGL(k_batch_bstep<3>, g, blk, 0, s, bd, P); break;
+      case 4: hipLaunchKernelGGL(k_batch_bstep<4>, g, blk, 0, s, bd, P); break;
+      case 5: hipLaunchKernelGGL(k_batch_bstep<5>, g, blk, 0, s, bd, P); break;
+      case 6: hipLaunchKernelGGL(k_batch_bstep<6>, g, blk, 0, s, bd, P); break;
+      case 7: hipLaunchKernelGGL(k_batch_bstep<7>, g, blk, 0, s, bd, P); break;
+      default: hipLaunchKernelGGL(k_batch_bstep<8>, g, blk, 0, s, bd, P); break;
     }
   }
   for (int P = 1; P <= EPI_PMAX; ++P) {
-    if (!(key & (1u << P))) continue;
+    if (!key.bstep[P]) continue;
     switch (P) {
       case 1: hipLaunchKernelGGL(k_batch_hard<1>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
       case 2: hipLaunchKernelGGL(k_batch_hard<2>, dim3(BATCH_HARD_GRID), dim3(64), 0, s, bd, P); break;
@@ -501,12 +523,13 @@ static void batch_iteration(epi_batch* bt, uint32_t key) {
   }
   const int prec = bt->precision;
   for (int c = 0; c < 8; ++c) {
-    if (!(key & (1u << (16 + c)))) continue;
+    const int g = key.dct[c];
+    if (!g) continue;
     const bool small = (c & 1) == 0;
-    if (c < 2) launch_batch_dct<false, 0>(s, prec, bd, c, 1, small);
-    else if (c < 4) launch_batch_dct<true, 0>(s, prec, bd, c, 2, small);
-    else if (c < 6) launch_batch_dct<true, 1>(s, prec, bd, c, 2, small);
-    else launch_batch_dct<false, 1>(s, prec, bd, c, 3, small);
+    if (c < 2) launch_batch_dct<false, 0>(s, prec, bd, c, 1, small, g);
+    else if (c < 4) launch_batch_dct<true, 0>(s, prec, bd, c, 2, small, g);
+    else if (c < 6) launch_batch_dct<true, 1>(s, prec, bd, c, 2, small, g);
+    else launch_batch_dct<false, 1>(s, prec, bd, c, 3, small, g);
   }
   hipLaunchKernelGGL(k_batch_finalize, dim3(bt->max_slots), dim3(256), 0, s, bd);
 }
@@ -515,7 +538,7 @@ EPI_API epi_status epi_batch_step(epi_batch* bt, int32_t* running) {
   if (!bt) return fail(EPI_EINVAL, "null argument");
   batch_enter(bt);
   if (bt->dirty) {
-    uint32_t key = 0;
+    BatchKey key;
     epi_status s = batch_rebuild(bt, &key);
     if (s != EPI_OK) return s;
     bt->dirty = false;

@@ -372,6 +372,9 @@ class Batch:
         """None while running, else the report dict (as Problem.solve_admm returns)."""
         L = _batch_sigs(lib())
         fin = C.c_int32(0)
+        _check(L.epi_batch_poll(self._h, int(slot), C.byref(fin), None))
+        if not fin.value:
+            return None
         n1 = self._maxit[slot]
         arrs = {k: (C.c_double * n1)() for k in ("r_pri", "r_dual", "eps_pri", "eps_dual")}
         rep = ADMMReport()

@@ -187,6 +187,60 @@ def _invert(fld: _Field, y: np.ndarray, sign: float, bmax: float) -> np.ndarray:
     return x
 
 
+def _lines_chunk(args):
+    """Undistorted and measured images of a contiguous range of PE lines (elementwise per
+    line, so the result does not depend on how the lines are split)."""
+    (nu, tau, eps, s, F, xx2, xx3, xcc, mu_c, sig, amp, shell_c, three_d, bmax) = args
+    sub = _Field.__new__(_Field)
+    sub.nu, sub.tau, sub.eps, sub.s, sub.F = nu, tau, eps, s, F
+    it = _image_lines(xcc, xx2, xx3, mu_c, sig, amp, shell_c, three_d)
+    res = [it]
+    for sign in (+1.0, -1.0):
+        xs = _invert(sub, xcc, sign, bmax)
+        _, db = sub.eval(xs, deriv=True)
+        res.append(_image_lines(xs, xx2, xx3, mu_c, sig, amp, shell_c, three_d)
+                   / (1.0 + sign * db))
+    return res
+
+
+_POOL = None
+_POOL_MIN_CELLS = 400_000     # smaller volumes are generated in-process
+
+
+def _pool_usable() -> bool:
+    """Spawned workers re-import the main module: only possible when it is a real file
+    (or absent, as under ``python -c``)."""
+    import os
+    import sys
+    f = getattr(sys.modules.get("__main__"), "__file__", None)
+    return _threads() > 1 and (f is None or os.path.exists(f))
+
+
+def _pool():
+    """Worker processes (spawned: they import numpy and this module only) for large
+    volumes; numpy's many small temporaries keep threads from scaling."""
+    global _POOL
+    if _POOL is None:
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        import atexit
+        _POOL = ProcessPoolExecutor(max_workers=_threads(), mp_context=mp.get_context("spawn"))
+        atexit.register(_POOL.shutdown, wait=True)
+    return _POOL
+
+
+def _run_chunks(jobs, parallel: bool):
+    global _POOL
+    if parallel:
+        from concurrent.futures.process import BrokenProcessPool
+        try:
+            return list(_pool().map(_lines_chunk, jobs))
+        except BrokenProcessPool:
+            _POOL.shutdown(wait=False, cancel_futures=True)
+            _POOL = None
+    return [_lines_chunk(j) for j in jobs]
+
+
 def generate(seed: int, m_user: Sequence[int], pe_axis: int, *, noise: float = 0.01,
              n_blobs: int | None = None, n_bumps: int | None = None,
              peak_vox: float | None = None, dmax: float | None = None) -> Volume:
@@ -247,32 +301,17 @@ def generate(seed: int, m_user: Sequence[int], pe_axis: int, *, noise: float = 0
     b_faces = fld.eval(xf)
     bmax = float(s * np.sum(np.max(np.abs(fld.F), axis=1)))   # bound on |b| anywhere
 
-    # Everything below is elementwise per PE line, so lines are processed in chunks on a
-    # thread pool (numpy releases the GIL); the result does not depend on the chunking.
-    bounds = np.linspace(0, L, min(L, 4 * _threads()) + 1).astype(int)
-    chunks = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    # Everything below is elementwise per PE line, so lines are processed in chunks (on
+    # worker processes for large volumes); the result does not depend on the chunking.
     x3_of_line = np.repeat(np.arange(m3), m2)
     x2_of_line = np.tile(np.arange(m2), m3)
-
-    def work(ab):
-        a, b_ = ab
-        sub = _Field.__new__(_Field)
-        sub.nu, sub.tau, sub.eps, sub.s = fld.nu, fld.tau, fld.eps, fld.s
-        sub.F = fld.F[:, a:b_]
-        xx2, xx3 = x2[x2_of_line[a:b_]], x3[x3_of_line[a:b_]]
-        xcc = xc[a:b_]
-        it = _image_lines(xcc, xx2, xx3, mu_c, sig, amp, shell_c, three_d)
-        res = [it]
-        for sign in (+1.0, -1.0):
-            xs = _invert(sub, xcc, sign, bmax)
-            _, db = sub.eval(xs, deriv=True)
-            res.append(_image_lines(xs, xx2, xx3, mu_c, sig, amp, shell_c, three_d)
-                       / (1.0 + sign * db))
-        return res
-
-    from concurrent.futures import ThreadPoolExecutor
-    with ThreadPoolExecutor(max_workers=_threads()) as ex:
-        parts = list(ex.map(work, chunks))
+    par = L * M >= _POOL_MIN_CELLS and _pool_usable()
+    bounds = np.linspace(0, L, min(L, 4 * _threads() if par else 1) + 1).astype(int)
+    chunks = [(int(a), int(b)) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+    jobs = [(fld.nu, fld.tau, fld.eps, fld.s, fld.F[:, a:b_], x2[x2_of_line[a:b_]],
+             x3[x3_of_line[a:b_]], xc[a:b_], mu_c, sig, amp, shell_c, three_d, bmax)
+            for a, b_ in chunks]
+    parts = _run_chunks(jobs, par)
     I_true = np.concatenate([p_[0] for p_ in parts], axis=0)
     Ip = np.concatenate([p_[1] for p_ in parts], axis=0)
     Im = np.concatenate([p_[2] for p_ in parts], axis=0)
