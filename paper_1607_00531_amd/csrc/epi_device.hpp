@@ -164,13 +164,15 @@ template <int P, int NA>
 __device__ __forceinline__ void stage_in_n(const float* const (&src)[NA], const int (&count)[NA],
                                            bool valid, float* lds, float (&dst)[NA][P],
                                            int lane) {
+  // P = ceil((M + 1) / 64) and count >= M, so only the last of the P loads can fall past
+  // the end of a line: the others are unconditional (given valid).
   float t[NA][P];
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const int i = lane + 64 * j;
-      t[a][j] = (valid && i < count[a]) ? src[a][i] : 0.0f;
+      t[a][j] = (valid && (j < P - 1 || i < count[a])) ? src[a][i] : 0.0f;
     }
 #pragma unroll
   for (int a = 0; a < NA; ++a)
@@ -199,7 +201,7 @@ __device__ __forceinline__ void stage_out_n(float* const (&dst)[NA], int count, 
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         const int t = lane + 64 * j;
-        if (t < count) dst[a][t] = lds[a * LineBuf<P>::SIZE + lds_pad(t)];
+        if (j < P - 1 || t < count) dst[a][t] = lds[a * LineBuf<P>::SIZE + lds_pad(t)];
       }
   }
   __syncthreads();
@@ -233,13 +235,17 @@ __device__ __forceinline__ void stage_out(float* __restrict__ dst, int count, bo
 // resulting 64-row tridiagonal system of block-last unknowns is solved by parallel
 // cyclic reduction across lanes; the interior rows follow by substitution.
 // ------------------------------------------------------------------------------------
+// Reciprocal by the hardware approximation (v_rcp_f32, 1 ulp) instead of the IEEE divide
+// sequence (about ten instructions): the line solves are bound by instruction issue.
+__device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <int P>
 __device__ __forceinline__ void wave_tridiag_solve(const float (&d)[P], const float (&e)[P],
                                                    float (&r)[P], int lane) {
   float ap[P], cp[P], rp[P];
   const float a0 = shfl_up0(e[P - 1], 1, lane);   // coupling of row P*lane to the row before
   {
-    const float inv = 1.0f / d[0];
+    const float inv = rcp_f(d[0]);
     ap[0] = a0 * inv;
     cp[0] = e[0] * inv;
     rp[0] = r[0] * inv;
@@ -247,7 +253,7 @@ __device__ __forceinline__ void wave_tridiag_solve(const float (&d)[P], const fl
 #pragma unroll
   for (int j = 1; j < P; ++j) {
     const float a = e[j - 1];
-    const float inv = 1.0f / (d[j] - a * cp[j - 1]);
+    const float inv = rcp_f(d[j] - a * cp[j - 1]);
     ap[j] = -a * ap[j - 1] * inv;
     cp[j] = e[j] * inv;
     rp[j] = (r[j] - a * rp[j - 1]) * inv;
@@ -271,22 +277,24 @@ __device__ __forceinline__ void wave_tridiag_solve(const float (&d)[P], const fl
   float rb = 1.0f - cp[P - 1] * An;
   float rc = (lane == 63) ? 0.0f : -cp[P - 1] * Cn;
   float rr = rp[P - 1] - cp[P - 1] * Rn;
+  // Parallel cyclic reduction. Before the step of distance s, every lane below s has
+  // ra = 0 and every lane at or above 64 - s has rc = 0 (true for s = 1 and kept by each
+  // step), so a lane without a partner at distance s gets a zero multiplier from its own
+  // finite shuffled values: no boundary branches are needed.
 #pragma unroll
   for (int s = 1; s < 64; s <<= 1) {
-    const bool hasm = lane >= s, hasp = lane + s < 64;
-    float am = __shfl_up(ra, s, 64), bm = __shfl_up(rb, s, 64), cm = __shfl_up(rc, s, 64),
-          xm = __shfl_up(rr, s, 64);
-    float aq = __shfl_down(ra, s, 64), bq = __shfl_down(rb, s, 64), cq = __shfl_down(rc, s, 64),
-          xq = __shfl_down(rr, s, 64);
-    if (!hasm) { am = 0.0f; bm = 1.0f; cm = 0.0f; xm = 0.0f; }
-    if (!hasp) { aq = 0.0f; bq = 1.0f; cq = 0.0f; xq = 0.0f; }
-    const float al = -ra / bm, ga = -rc / bq;
+    const float ib = rcp_f(rb);
+    const float am = __shfl_up(ra, s, 64), ibm = __shfl_up(ib, s, 64),
+                cm = __shfl_up(rc, s, 64), xm = __shfl_up(rr, s, 64);
+    const float aq = __shfl_down(ra, s, 64), ibq = __shfl_down(ib, s, 64),
+                cq = __shfl_down(rc, s, 64), xq = __shfl_down(rr, s, 64);
+    const float al = -ra * ibm, ga = -rc * ibq;
     const float na = al * am, nc = ga * cq;
     const float nb = rb + al * cm + ga * aq;
     const float nr = rr + al * xm + ga * xq;
     ra = na; rb = nb; rc = nc; rr = nr;
   }
-  const float X = rr / rb;
+  const float X = rr * rcp_f(rb);
   const float Xp = shfl_up0(X, 1, lane);
 #pragma unroll
   for (int j = 0; j < P; ++j) r[j] = R[j] - A[j] * Xp - C[j] * X;

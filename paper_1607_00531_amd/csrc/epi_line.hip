@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
                                                const DevState* st) {
   if (dsrc != nullptr && st->ls_done) return;
   __shared__ float sbuf[EPI_LINE_WAVES][7][LineBuf<P>::SIZE];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = xcd_remap(blockIdx.x, a.nblk);
   const int line = blk * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_pcg_init(LineArgs a, int precond,
                                                   float* __restrict__ z, float* __restrict__ p,
                                                   double* partial) {
   __shared__ float sbuf[EPI_LINE_WAVES][LineBuf<P>::SIZE];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
   const int lc = valid ? line : 0;
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(LineArgs a, int precond,
                                                     const DevState* st) {
   if (st->pcg_done) return;
   __shared__ float sbuf[EPI_LINE_WAVES][LineBuf<P>::SIZE];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
   const int lc = valid ? line : 0;
@@ -279,7 +279,7 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
                                                     DevState* st) {
   if (st->admm_done) return;
   __shared__ float sbuf[EPI_LINE_WAVES][5][LineBuf<P>::SIZE];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
   const bool hard = bstep_line_body<P>(a, (float)st->rho, bvec, zvec, uvec, wvec,

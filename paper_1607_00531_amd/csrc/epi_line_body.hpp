@@ -16,19 +16,18 @@ namespace epi {
 // (the right-hand segment at a knot). The floor is taken of the displacement alone and
 // the integer cell index added afterwards: rounding c + disp in float32 would move small
 // displacements (|disp| < ulp(c) / 2) onto the knot and pick the wrong segment.
+// Branch-free: both samples are read at clamped (always valid) indices and the values
+// outside the image are selected to zero afterwards.
 __device__ __forceinline__ void interp_lds(const float* sT, int M, int c, float disp,
                                            float inv_hp, float& val, float& der) {
   disp = fminf(fmaxf(disp, -(float)(2 * M + 4)), (float)(2 * M + 4));
   const float fl = floorf(disp);
   const int k = c + (int)fl;
   const float f = disp - fl;
-  if (k < -1 || k > M - 1) {
-    val = 0.0f;
-    der = 0.0f;
-    return;
-  }
-  const float t0 = (k >= 0) ? sT[lds_pad(k)] : 0.0f;
-  const float t1 = (k + 1 <= M - 1) ? sT[lds_pad(k + 1)] : 0.0f;
+  const int k0 = min(max(k, 0), M - 1), k1 = min(max(k + 1, 0), M - 1);
+  float t0 = sT[lds_pad(k0)], t1 = sT[lds_pad(k1)];
+  t0 = (k >= 0 && k <= M - 1) ? t0 : 0.0f;
+  t1 = (k >= -1 && k <= M - 2) ? t1 : 0.0f;
   val = fmaf(f, t1 - t0, t0);
   der = (t1 - t0) * inv_hp;
 }
@@ -50,24 +49,19 @@ __device__ __forceinline__ void eval_cells(const LineArgs& a, const float (&b)[P
   for (int j = 0; j < P; ++j) {
     const int c = P * lane + j;
     const float bR = (j < P - 1) ? b[j + 1] : bnext;
-    if (c < a.M) {
-      const float aidx = 0.5f * (b[j] + bR) * a.inv_hp;
-      const float g = (bR - b[j]) * a.inv_hp;
-      float ipv, ipd, imv, imd;
-      interp_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
-      interp_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
-      const float gp = 1.0f + g, gm = 1.0f - g;
-      C.g[j] = g;
-      C.r[j] = ipv * gp - imv * gm;
-      const float Sd = ipd * gp + imd * gm, Tv = ipv + imv;
-      C.Jl[j] = 0.5f * Sd - Tv * a.inv_hp;
-      C.Jr[j] = 0.5f * Sd + Tv * a.inv_hp;
-    } else {
-      C.g[j] = 0.0f;
-      C.r[j] = 0.0f;
-      C.Jl[j] = 0.0f;
-      C.Jr[j] = 0.0f;
-    }
+    // computed for every slot (interp_lds is safe for any index), zeroed past the line
+    const float aidx = 0.5f * (b[j] + bR) * a.inv_hp;
+    const float g = (bR - b[j]) * a.inv_hp;
+    float ipv, ipd, imv, imd;
+    interp_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
+    interp_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
+    const float gp = 1.0f + g, gm = 1.0f - g;
+    const float Sd = ipd * gp + imd * gm, Tv = ipv + imv;
+    const bool in = c < a.M;
+    C.g[j] = in ? g : 0.0f;
+    C.r[j] = in ? ipv * gp - imv * gm : 0.0f;
+    C.Jl[j] = in ? 0.5f * Sd - Tv * a.inv_hp : 0.0f;
+    C.Jr[j] = in ? 0.5f * Sd + Tv * a.inv_hp : 0.0f;
   }
 }
 
@@ -116,17 +110,15 @@ __device__ __forceinline__ void qp_data(const LineArgs& a, float rho, const floa
   for (int j = 0; j < P; ++j) {
     const int i = P * lane + j;
     g[j] = C.g[j];
-    if (i < NF) {
-      c[j] = a.v * (C.Jl[j] * C.r[j] + rpJ[j]) +
-             a.alpha * a.v * (gprev[j] - C.g[j]) * a.inv_hp + rv * (b[j] - z[j] + u[j]);
-      const float ncell = (float)((i < a.M) + (i >= 1));
-      Gd[j] = a.v * (C.Jl[j] * C.Jl[j] + JrPrev[j] * JrPrev[j]) + qa * ncell + rv;
-      Go[j] = (i < a.M) ? a.v * C.Jl[j] * C.Jr[j] - qa : 0.0f;
-    } else {
-      c[j] = 0.0f;
-      Gd[j] = 1.0f;
-      Go[j] = 0.0f;
-    }
+    // slots past the last face get the identity row (c = 0, G = I)
+    const bool in = i < NF;
+    const float cj = a.v * (C.Jl[j] * C.r[j] + rpJ[j]) +
+                     a.alpha * a.v * (gprev[j] - C.g[j]) * a.inv_hp + rv * (b[j] - z[j] + u[j]);
+    const float ncell = (float)((i < a.M) + (i >= 1));
+    const float gd = a.v * (C.Jl[j] * C.Jl[j] + JrPrev[j] * JrPrev[j]) + qa * ncell + rv;
+    c[j] = in ? cj : 0.0f;
+    Gd[j] = in ? gd : 1.0f;
+    Go[j] = (i < a.M) ? a.v * C.Jl[j] * C.Jr[j] - qa : 0.0f;
   }
 }
 
