@@ -83,7 +83,8 @@ __global__ __launch_bounds__(64) void k_batch_hard(BatchDev* bd, int cls) {
 }
 
 template <int PREC, bool FUSED, int EPI, int KSM, int SLOTS>
-__global__ __launch_bounds__(256) void k_batch_dct(BatchDev* bd, int cls, int pass) {
+__global__ __launch_bounds__(PREC == 1 ? 64 * EPI_DCT_NW : 256) void k_batch_dct(BatchDev* bd,
+                                                                                 int cls, int pass) {
   const RangeTable& T = bd->dt[cls];
   const int nr = T.n;
   if (nr == 0) return;
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_batch_dct(BatchDev* bd, int cls, int pa
   const int c0 = (local % g.col_tiles) * DCT_NT;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   if (PREC == 1)
-    dct_bf16_body<FUSED, EPI, KSM, SLOTS>(g, batch, c0, local,
+    dct_bf16_body<FUSED, EPI, KSM, EPI_DCT_NW>(g, batch, c0, local,
                                           reinterpret_cast<unsigned short*>(lds_raw));
   else
     dct_f32_body<FUSED, EPI, KSM * 8, SLOTS>(g, batch, c0, local,
@@ -130,7 +131,7 @@ template <bool FUSED, int EPI>
 static void launch_batch_dct(hipStream_t s, int prec, BatchDev* bd, int cls, int pass, bool small,
                              int grid) {
   const size_t lds = dct_class_lds(prec, small);
-  const dim3 g(grid), blk(256);
+  const dim3 g(grid), blk(prec == 1 ? 64 * EPI_DCT_NW : 256);
   if (prec == 1) {
     if (small) hipLaunchKernelGGL((k_batch_dct<1, FUSED, EPI, 4, 2>), g, blk, lds, s, bd, cls, pass);
     else hipLaunchKernelGGL((k_batch_dct<1, FUSED, EPI, 8, 4>), g, blk, lds, s, bd, cls, pass);

@@ -24,12 +24,12 @@ namespace epi {
 
 // Single-volume kernels: one workgroup per (batch entry, 64-column tile).
 template <bool FUSED, int EPI, int KSM, int SLOTS>
-__global__ __launch_bounds__(256) void k_dct_bf16(GemmArgs g) {
+__global__ __launch_bounds__(64 * EPI_DCT_NW) void k_dct_bf16(GemmArgs g) {
   if (g.done != nullptr && *g.done) return;
   extern __shared__ __attribute__((aligned(16))) unsigned short lds_bf[];
   int batch, c0;
   const int t = dct_tile(g, batch, c0);
-  dct_bf16_body<FUSED, EPI, KSM, SLOTS>(g, batch, c0, t, lds_bf);
+  dct_bf16_body<FUSED, EPI, KSM, EPI_DCT_NW>(g, batch, c0, t, lds_bf);
 }
 
 template <bool FUSED, int EPI, int KSM, int SLOTS>
@@ -43,12 +43,12 @@ __global__ __launch_bounds__(256) void k_dct_f32(GemmArgs g) {
 
 template <bool FUSED, int EPI, int KSM, int SLOTS>
 static void launch_dct_t(hipStream_t s, int prec, const GemmArgs& g) {
-  const dim3 grid(g.nbatch * g.col_tiles), blk(256);
+  const dim3 grid(g.nbatch * g.col_tiles);
   const size_t lds = dct_lds_bytes(prec, g);
   if (prec == 1)
-    hipLaunchKernelGGL((k_dct_bf16<FUSED, EPI, KSM, SLOTS>), grid, blk, lds, s, g);
+    hipLaunchKernelGGL((k_dct_bf16<FUSED, EPI, KSM, SLOTS>), grid, dim3(64 * EPI_DCT_NW), lds, s, g);
   else
-    hipLaunchKernelGGL((k_dct_f32<FUSED, EPI, KSM * 8, SLOTS>), grid, blk, lds, s, g);
+    hipLaunchKernelGGL((k_dct_f32<FUSED, EPI, KSM * 8, SLOTS>), grid, dim3(256), lds, s, g);
 }
 
 // rows <= 128: 4 contraction steps of 32 and 2 row tiles per wave; rows <= 256: 8 and 4

@@ -12,21 +12,37 @@ namespace epi {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned short us8 __attribute__((ext_vector_type(8)));
-typedef unsigned short us4 __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 #define DCT_NT 64          // columns per workgroup
 
-__device__ __forceinline__ unsigned short f2bf(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+// wavefronts per workgroup of the split-bfloat16 tile kernels (float32 kernels use 4)
+#ifndef EPI_DCT_NW
+#define EPI_DCT_NW 8
+#endif
+
+// Split of two floats into bfloat16 pairs a = a_hi + a_lo (both rounded to nearest even):
+// one v_cvt_pk_bf16_f32 per pair for each part. Packed as (first element in the low half).
+__device__ __forceinline__ void split_bf2(float a, float b, unsigned& hi, unsigned& lo) {
+  const f2v v = {a, b};
+  const unsigned h = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf2v));
+  const f2v hf = {__uint_as_float(h << 16), __uint_as_float(h & 0xffff0000u)};
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(v - hf, bf2v));
+  hi = h;
 }
-__device__ __forceinline__ float bf2f(unsigned short h) {
-  return __uint_as_float(((unsigned)h) << 16);
+
+// Access at a wave-uniform base plus a 32-bit byte offset: the compiler keeps the base in
+// scalar registers and addresses with the offset alone (no per-lane 64-bit arithmetic).
+template <typename T>
+__device__ __forceinline__ T ld_at(const void* base, unsigned boff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
 }
-__device__ __forceinline__ void split_bf(float x, unsigned short& hi, unsigned short& lo) {
-  hi = f2bf(x);
-  lo = f2bf(x - bf2f(hi));
+template <typename T>
+__device__ __forceinline__ void st_at(void* base, unsigned boff, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
 
 // Tile index -> (batch, first column), walking each XCD over a contiguous range.
@@ -38,14 +54,15 @@ __device__ __forceinline__ int dct_tile(const GemmArgs& g, int& batch, int& c0) 
   return t;
 }
 
-// Accumulators -> LDS tile [row][col] (float32, row stride DCT_NT + 4), scaled per row.
-template <int SLOTS>
+// Accumulators -> LDS tile [row][col] (float32, row stride DCT_NT + 4); row tile
+// rt = wave + NW s.
+template <int SLOTS, int NW>
 __device__ __forceinline__ void acc_to_lds(float* T, const f4 (&acc)[SLOTS][4], int wave,
                                            int lane, int nslot) {
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s) {
     if (s < nslot) {
-      const int r0 = (wave + 4 * s) * 16 + (lane >> 4) * 4;
+      const int r0 = (wave + NW * s) * 16 + (lane >> 4) * 4;
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
@@ -54,158 +71,208 @@ __device__ __forceinline__ void acc_to_lds(float* T, const f4 (&acc)[SLOTS][4], 
   }
 }
 
-// Epilogue of the last pass from the LDS tile, one row of 64 consecutive columns per 64
-// threads (coalesced). EPI 0: store. EPI 1: ADMM u-step and residual sums:
-// z_new = value, u_new = u + b - z_new (eq. admmStep3); sums |b - z|^2, |z - z_old|^2,
-// |z|^2, |u|^2, |b|^2 into the partial buffer.
-template <int EPI>
+// Epilogue of the last pass from the LDS tile, one row of 64 consecutive columns per
+// wavefront (coalesced; the row is uniform over the wavefront). EPI 0: store. EPI 1: ADMM
+// u-step and residual sums: z_new = value, u_new = u + b - z_new (eq. admmStep3); sums
+// |b - z|^2, |z - z_old|^2, |z|^2, |u|^2, |b|^2 into the partial buffer.
+template <int EPI, int NW>
 __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const float* T, size_t bofs,
                                               int c0, int pslot) {
   double acc[NQ_ADMM_E] = {0, 0, 0, 0, 0};
   const int col = threadIdx.x & (DCT_NT - 1);
+  const unsigned col4 = (unsigned)col * 4u;
   const bool cok = c0 + col < g.ncol;
-  for (int row = threadIdx.x / DCT_NT; row < g.rows; row += 256 / DCT_NT) {
-    if (!cok) continue;
-    const float val = T[row * (DCT_NT + 4) + col];
-    const size_t idx = bofs + (size_t)row * g.ld + c0 + col;
-    if (EPI == 0) {
-      g.out[idx] = val;
-    } else {
-      const float zo = g.z[idx];
-      const float uo = g.u[idx];
-      const float bb = g.b[idx];
-      const float r = bb - val;
-      const float un = uo + r;
-      g.z[idx] = val;
-      g.u[idx] = un;
-      const float dz = val - zo;
-      acc[0] += (double)r * r;
-      acc[1] += (double)dz * dz;
-      acc[2] += (double)val * val;
-      acc[3] += (double)un * un;
-      acc[4] += (double)bb * bb;
+  const int r0 = __builtin_amdgcn_readfirstlane(threadIdx.x / DCT_NT);
+  constexpr int RS = 64 * NW / DCT_NT;
+  if (EPI == 0) {
+    float* ob = g.out + bofs + c0;
+    for (int row = r0; row < g.rows; row += RS)
+      if (cok) st_at<float>(ob + (size_t)row * g.ld, col4, T[row * (DCT_NT + 4) + col]);
+  } else {
+    // U rows per thread in flight: all their loads are issued before the first store
+    // (the stores to z and u could alias the loads as far as the compiler knows)
+    constexpr int U = 8;
+    const float* bb0 = g.b + bofs + c0;
+    float* zb0 = g.z + bofs + c0;
+    float* ub0 = g.u + bofs + c0;
+    for (int rb = r0; rb < g.rows; rb += RS * U) {
+      float zo[U], uo[U], bb[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int row = rb + RS * q;
+        const size_t ro = (size_t)(row < g.rows ? row : 0) * g.ld;
+        const bool ok = cok && row < g.rows;
+        zo[q] = ok ? ld_at<float>(zb0 + ro, col4) : 0.0f;
+        uo[q] = ok ? ld_at<float>(ub0 + ro, col4) : 0.0f;
+        bb[q] = ok ? ld_at<float>(bb0 + ro, col4) : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const int row = rb + RS * q;
+        if (cok && row < g.rows) {
+          const size_t ro = (size_t)row * g.ld;
+          const float val = T[row * (DCT_NT + 4) + col];
+          const float r = bb[q] - val;
+          const float un = uo[q] + r;
+          st_at<float>(zb0 + ro, col4, val);
+          st_at<float>(ub0 + ro, col4, un);
+          const float dz = val - zo[q];
+          acc[0] += (double)r * r;
+          acc[1] += (double)dz * dz;
+          acc[2] += (double)val * val;
+          acc[3] += (double)un * un;
+          acc[4] += (double)bb[q] * bb[q];
+        }
+      }
     }
+    block_partials<NQ_ADMM_E>(acc, g.partial, pslot);
   }
-  if (EPI == 1) block_partials<NQ_ADMM_E>(acc, g.partial, pslot);
 }
 
 // ------------------------------------------------------------------------------------
-// split-bfloat16 variant. KSM: maximum contraction steps of 32 (rows <= 32 KSM);
-// SLOTS: 16-row tiles per wave (rows <= 64 SLOTS).
+// split-bfloat16 variant. KSM: maximum contraction steps of 32 (rows <= 32 KSM); NW
+// wavefronts per workgroup; SLOTS = 2 KSM / NW row tiles of 16 per wavefront.
 // ------------------------------------------------------------------------------------
-// acc[s][ct] += A(row tile wave + 4 s) * B(LDS tile, column tile ct) over all contraction
-// steps. The A fragments of step ks + 1 are loaded while the products of step ks run.
-template <int SLOTS>
+// acc[s][ct] += A(row tile wave + NW s) * B(LDS tile, column tile ct) over all contraction
+// steps. The A fragments stream from L2 PD steps ahead of the products that use them; the
+// step loop is unrolled over its compile-time bound KSM so that the fragment ring stays in
+// registers.
+template <int SLOTS, int KSM, int PD, int NW>
 __device__ __forceinline__ void gemm_bf16(const us8* __restrict__ A, size_t frag_stride, int KS,
                                           int wave, int lane, int nslot,
                                           const unsigned short* Lhi, const unsigned short* Llo,
                                           int KP, f4 (&acc)[SLOTS][4]) {
-  us8 nh[SLOTS], nl[SLOTS];
+  // fragment (row tile rt, step ks) of lane l sits at ((rt * KS + ks) * 64 + l) * 16 bytes;
+  // rt = wave + NW s is uniform, so only lane * 16 is a per-lane offset
+  const us8* Alo = A + frag_stride;
+  const unsigned lane16 = (unsigned)lane * 16u;
+  us8 fh[KSM][SLOTS], fl[KSM][SLOTS];
 #pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    if (s < nslot) {
-      const size_t fi = ((size_t)(wave + 4 * s) * KS) * 64 + lane;
-      nh[s] = A[fi];
-      nl[s] = A[frag_stride + fi];
-    }
-  }
-  for (int ks = 0; ks < KS; ++ks) {
-    us8 ch[SLOTS], cl[SLOTS];
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      ch[s] = nh[s];
-      cl[s] = nl[s];
-    }
-    if (ks + 1 < KS) {
+  for (int ks = 0; ks < PD && ks < KSM; ++ks) {
+    if (ks < KS) {
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
         if (s < nslot) {
-          const size_t fi = ((size_t)(wave + 4 * s) * KS + ks + 1) * 64 + lane;
-          nh[s] = A[fi];
-          nl[s] = A[frag_stride + fi];
+          const size_t fu = ((size_t)(wave + NW * s) * KS + ks) * 64;
+          fh[ks][s] = ld_at<us8>(A + fu, lane16);
+          fl[ks][s] = ld_at<us8>(Alo + fu, lane16);
         }
       }
     }
-    bf16x8 bh[4], bl[4];
+  }
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const int col = ct * 16 + (lane & 15);
-      const int k0 = ks * 32 + (lane >> 4) * 8;
-      bh[ct] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Lhi[col * KP + k0]));
-      bl[ct] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Llo[col * KP + k0]));
-    }
+  for (int ks = 0; ks < KSM; ++ks) {
+    if (ks < KS) {
+      if (ks + PD < KSM && ks + PD < KS) {
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-      if (s < nslot) {
-        const bf16x8 ah = __builtin_bit_cast(bf16x8, ch[s]);
-        const bf16x8 al = __builtin_bit_cast(bf16x8, cl[s]);
+        for (int s = 0; s < SLOTS; ++s) {
+          if (s < nslot) {
+            const size_t fu = ((size_t)(wave + NW * s) * KS + ks + PD) * 64;
+            fh[(ks + PD) % KSM][s] = ld_at<us8>(A + fu, lane16);
+            fl[(ks + PD) % KSM][s] = ld_at<us8>(Alo + fu, lane16);
+          }
+        }
+      }
+      bf16x8 bh[4], bl[4];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-          acc[s][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[s][ct], 0, 0, 0);
-          acc[s][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[s][ct], 0, 0, 0);
-          acc[s][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[s][ct], 0, 0, 0);
+      for (int ct = 0; ct < 4; ++ct) {
+        const int col = ct * 16 + (lane & 15);
+        const int k0 = ks * 32 + (lane >> 4) * 8;
+        bh[ct] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Lhi[col * KP + k0]));
+        bl[ct] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Llo[col * KP + k0]));
+      }
+#pragma unroll
+      for (int s = 0; s < SLOTS; ++s) {
+        if (s < nslot) {
+          const bf16x8 ah = __builtin_bit_cast(bf16x8, fh[ks][s]);
+          const bf16x8 al = __builtin_bit_cast(bf16x8, fl[ks][s]);
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) {
+            acc[s][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[ct], acc[s][ct], 0, 0, 0);
+            acc[s][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[ct], acc[s][ct], 0, 0, 0);
+            acc[s][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[ct], acc[s][ct], 0, 0, 0);
+          }
         }
       }
     }
   }
 }
 
+// prefetch depth of the A fragments (contraction steps ahead)
+#ifndef EPI_GEMM_PD_SMALL
+#define EPI_GEMM_PD_SMALL 4
+#endif
+#ifndef EPI_GEMM_PD_BIG
+#define EPI_GEMM_PD_BIG 2
+#endif
+template <int KSM>
+struct GemmPD {
+  static constexpr int value = KSM <= 4 ? EPI_GEMM_PD_SMALL : EPI_GEMM_PD_BIG;
+};
+
 // One 64-column tile of one batch entry: fill, product(s), epilogue. pslot = index of this
-// tile's partial sums (EPI 1). Every thread of the workgroup must call it.
-template <bool FUSED, int EPI, int KSM, int SLOTS>
+// tile's partial sums (EPI 1). Every thread of the workgroup (NW wavefronts) must call it.
+// Rows up to 32 KSM; row tile rt belongs to wave rt % NW.
+template <bool FUSED, int EPI, int KSM, int NW>
 __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int c0, int pslot,
                                               unsigned short* lds_bf) {
+  constexpr int SLOTS = 2 * KSM / NW;
+  constexpr int NIT = (4 * KSM + NW - 1) / NW;   // 8-row groups per thread in the fill
   const int KP = g.KS * 32 + 8;
   unsigned short* Lhi = lds_bf;
   unsigned short* Llo = lds_bf + DCT_NT * KP;
   const size_t bofs = (size_t)batch * g.bstride;
-  const float* in = g.in + bofs;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float* in = g.in + bofs + c0;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-  // fill: thread handles (column, group of 8 consecutive rows) for KS such pairs; all
-  // global loads are issued before the first conversion
+  // fill: thread handles (column = lane, group kg = wave + NW it of 8 consecutive rows) for
+  // the 4 KS groups; the rows are uniform over the wavefront; all global loads are issued
+  // before the first conversion
   {
-    float v[KSM][8];
+    const unsigned lane4 = (unsigned)lane * 4u;
+    const bool cok = c0 + lane < g.ncol;
+    const int ngroups = 4 * g.KS;
+    float v[NIT][8];
 #pragma unroll
-    for (int it = 0; it < KSM; ++it) {
-      const int pi = threadIdx.x + 256 * it;
-      const int col = pi & (DCT_NT - 1), kg = pi / DCT_NT;
-      const bool ok = it < g.KS && c0 + col < g.ncol;
+    for (int it = 0; it < NIT; ++it) {
+      const int kg = wave + NW * it;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int k = kg * 8 + e;
-        v[it][e] = (ok && k < g.rows) ? in[(size_t)k * g.ld + c0 + col] : 0.0f;
+        v[it][e] = (kg < ngroups && k < g.rows && cok) ? ld_at<float>(in + (size_t)k * g.ld, lane4)
+                                                       : 0.0f;
       }
     }
 #pragma unroll
-    for (int it = 0; it < KSM; ++it) {
-      if (it < g.KS) {
-        const int pi = threadIdx.x + 256 * it;
-        const int col = pi & (DCT_NT - 1), kg = pi / DCT_NT;
-        us8 hv, lv;
+    for (int it = 0; it < NIT; ++it) {
+      const int kg = wave + NW * it;
+      if (kg < ngroups) {
+        const int col = lane;
+        u4v hv, lv;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          unsigned short h, l;
-          split_bf(v[it][e], h, l);
+        for (int e = 0; e < 4; ++e) {
+          unsigned h, l;
+          split_bf2(v[it][2 * e], v[it][2 * e + 1], h, l);
           hv[e] = h;
           lv[e] = l;
         }
-        *reinterpret_cast<us8*>(&Lhi[col * KP + kg * 8]) = hv;
-        *reinterpret_cast<us8*>(&Llo[col * KP + kg * 8]) = lv;
+        *reinterpret_cast<u4v*>(&Lhi[col * KP + kg * 8]) = hv;
+        *reinterpret_cast<u4v*>(&Llo[col * KP + kg * 8]) = lv;
       }
     }
   }
   __syncthreads();
 
-  const int nslot = (g.RT - wave + 3) / 4;   // row tiles rt = wave + 4 s
+  const int nslot = (g.RT - wave + NW - 1) / NW;   // row tiles rt = wave + NW s
   f4 acc[SLOTS][4];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[s][ct] = f4{0.f, 0.f, 0.f, 0.f};
   const size_t frag_stride = (size_t)g.RT * g.KS * 64;   // hi block, then lo block
-  gemm_bf16<SLOTS>(reinterpret_cast<const us8*>(g.A1), frag_stride, g.KS, wave, lane, nslot,
-                   Lhi, Llo, KP, acc);
+  gemm_bf16<SLOTS, KSM, GemmPD<KSM>::value, NW>(reinterpret_cast<const us8*>(g.A1), frag_stride,
+                                                g.KS, wave, lane, nslot, Lhi, Llo, KP, acc);
 
   if (FUSED) {
     // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)), then the inverse
@@ -215,40 +282,40 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (s < nslot) {
-        const int rt = wave + 4 * s;
+        const int rt = wave + NW * s;
         const int r0 = rt * 16 + (lane >> 4) * 4;
         float sc[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = r0 + r;
-          sc[r] = (row < g.rows) ? rho / (rho + g.alpha * (g.lam_row[row] + lb)) : 0.0f;
+          sc[r] = (row < g.rows) ? rho * rcp_f(rho + g.alpha * (g.lam_row[row] + lb)) : 0.0f;
         }
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
           const int col = ct * 16 + (lane & 15);
-          us4 hv, lv;
+          u2v hv, lv;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            unsigned short h, l;
-            split_bf(acc[s][ct][r] * sc[r], h, l);
+          for (int r = 0; r < 2; ++r) {
+            unsigned h, l;
+            split_bf2(acc[s][ct][2 * r] * sc[2 * r], acc[s][ct][2 * r + 1] * sc[2 * r + 1], h, l);
             hv[r] = h;
             lv[r] = l;
           }
-          *reinterpret_cast<us4*>(&Lhi[col * KP + r0]) = hv;
-          *reinterpret_cast<us4*>(&Llo[col * KP + r0]) = lv;
+          *reinterpret_cast<u2v*>(&Lhi[col * KP + r0]) = hv;
+          *reinterpret_cast<u2v*>(&Llo[col * KP + r0]) = lv;
           acc[s][ct] = f4{0.f, 0.f, 0.f, 0.f};
         }
       }
     }
     __syncthreads();
-    gemm_bf16<SLOTS>(reinterpret_cast<const us8*>(g.A2), frag_stride, g.KS, wave, lane, nslot,
-                     Lhi, Llo, KP, acc);
+    gemm_bf16<SLOTS, KSM, GemmPD<KSM>::value, NW>(reinterpret_cast<const us8*>(g.A2), frag_stride,
+                                                  g.KS, wave, lane, nslot, Lhi, Llo, KP, acc);
   }
   __syncthreads();   // the LDS tile is reused for the output
   float* T = reinterpret_cast<float*>(lds_bf);
-  acc_to_lds<SLOTS>(T, acc, wave, lane, nslot);
+  acc_to_lds<SLOTS, NW>(T, acc, wave, lane, nslot);
   __syncthreads();
-  tile_epilogue<EPI>(g, T, bofs, c0, pslot);
+  tile_epilogue<EPI, NW>(g, T, bofs, c0, pslot);
   __syncthreads();   // LDS free for the next tile
 }
 
@@ -317,7 +384,7 @@ __device__ __forceinline__ void dct_f32_body(const GemmArgs& g, int batch, int c
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = r0 + r;
-          const float sc = (row < g.rows) ? rho / (rho + g.alpha * (g.lam_row[row] + lb)) : 0.0f;
+          const float sc = (row < g.rows) ? rho * rcp_f(rho + g.alpha * (g.lam_row[row] + lb)) : 0.0f;
 #pragma unroll
           for (int ct = 0; ct < 4; ++ct) lds_f[row * LD + ct * 16 + (lane & 15)] = acc[s][ct][r] * sc;
         }
@@ -329,9 +396,9 @@ __device__ __forceinline__ void dct_f32_body(const GemmArgs& g, int batch, int c
     gemm_f32<SLOTS>(reinterpret_cast<const float*>(g.A2), g.KS, wave, lane, nslot, lds_f, acc);
   }
   __syncthreads();
-  acc_to_lds<SLOTS>(lds_f, acc, wave, lane, nslot);
+  acc_to_lds<SLOTS, 4>(lds_f, acc, wave, lane, nslot);
   __syncthreads();
-  tile_epilogue<EPI>(g, lds_f, bofs, c0, pslot);
+  tile_epilogue<EPI, 4>(g, lds_f, bofs, c0, pslot);
   __syncthreads();
 }
 
