@@ -44,6 +44,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def mfma_flops(M, m2, m3, precision):
+    """Matrix-core flops each DCT pass executes (dense products over the unpadded transform
+    lengths; the split-bf16 form runs three products per multiply-add)."""
+    n = (M + 1) * m2 * m3
+    k = 3 if precision == "mixed" else 1
+    return {"dct_axis3": k * 2 * m3 * n, "dct_axis2_fused": k * 2 * 2 * m2 * n,
+            "dct_last_epilogue": k * 2 * m3 * n}
+
+
 def algorithmic_bytes(M, m2, m3):
     """HBM bytes each kernel family must move per launch (float32 arrays)."""
     n = (M + 1) * m2 * m3
@@ -92,7 +101,8 @@ def percentile(xs, q):
 
 def cpu_baseline(vol, gpu_iters_mean, iters):
     """The FP64 oracle on this host: `iters` ADMM iterations of one volume, scaled by the
-    GPU's mean iteration count to solve one volume."""
+    GPU's mean iteration count to solve one volume. Also returns the oracle's last two
+    iterates and histories, against which the GPU result of the same sample is checked."""
     import oracle as O
     try:
         from threadpoolctl import threadpool_info
@@ -102,19 +112,61 @@ def cpu_baseline(vol, gpu_iters_mean, iters):
     P = O.make_problem(vol.Ip, vol.Im, vol.h, ALPHA, BETA)
     b = np.zeros((P.L, P.M + 1))
     z, u = b.copy(), b.copy()
+    hist = {"r_pri": [], "r_dual": []}
+    prev = None
     t0 = time.perf_counter()
     for _ in range(iters):
+        prev = (b, z, u)
         bn, _, _ = O.bstep(P, b, z, u, RHO)
         zn = O.zstep(P, bn + u, RHO)
         u = u + bn - zn
+        rp, rd, _, _ = O.admm_residuals(P, bn, zn, z, u, RHO, 0.0, 0.0)
+        hist["r_pri"].append(rp)
+        hist["r_dual"].append(rd)
         b, z = bn, zn
     dt = (time.perf_counter() - t0) / iters
-    return {"value": 1.0 / (dt * gpu_iters_mean), "unit": "volumes/s", "cores": int(blas),
+    base = {"value": 1.0 / (dt * gpu_iters_mean), "unit": "volumes/s", "cores": int(blas),
             "kind": "oracle",
             "sample": f"{iters} FP64 ADMM iterations of one 240x200x110 volume "
-                      f"({dt:.2f} s/iteration) x {gpu_iters_mean:.1f} iterations per solve "
-                      f"(mean of the GPU solves); numpy elementwise single-threaded, "
-                      f"BLAS threads {blas}"}
+                      f"({dt:.2f} s/iteration, {dt * iters:.1f} s) x {gpu_iters_mean:.1f} "
+                      f"iterations per solve (mean of the GPU solves); numpy elementwise "
+                      f"single-threaded, BLAS threads {blas}"}
+    ref = {"P": P, "prev": prev, "last": (b, z, u), "hist": hist, "J": O.objective(P, b)["J"]}
+    return base, ref
+
+
+def oracle_error(prob, ref, iters, shape):
+    """Error of the GPU (mixed precision, the timed configuration) against the oracle on
+    the cpu_baseline sample: the whole trajectory of `iters` iterations from zero, and one
+    iteration from the oracle's iterate iters - 1 (the per-step parity criterion)."""
+    import torch
+    P = ref["P"]
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.tensor(np.ascontiguousarray(a).reshape(shape), dtype=torch.float32, device=dev)
+    vox = lambda g, c: float(np.abs(g.cpu().numpy().reshape(P.L, -1) - c).max() / P.hp)
+    b, z, u = (torch.zeros(shape, device=dev) for _ in range(3))
+    rep = prob.solve_admm(b, z, u, rho=RHO, max_iter=iters, eps_abs=0.0, eps_rel=0.0,
+                          check_every=16)
+    J = prob.objective(b, True)["J"]
+    hrel = max(abs(a - c) / abs(c) for key in ("r_pri", "r_dual")
+               for a, c in zip(rep[key], ref["hist"][key]))
+    traj = {"iters": iters, "b_vox": vox(b, ref["last"][0]), "z_vox": vox(z, ref["last"][1]),
+            "u_vox": vox(u, ref["last"][2]), "J_rel": abs(J - ref["J"]) / abs(ref["J"]),
+            "hist_rel_max": hrel}
+    b, z, u = (T(x) for x in ref["prev"])
+    rep = prob.solve_admm(b, z, u, rho=RHO, max_iter=1, eps_abs=0.0, eps_rel=0.0, check_every=16)
+    scale = max(float(np.linalg.norm(ref["last"][0])), float(np.linalg.norm(ref["last"][1])))
+    dp = abs(rep["r_pri"][0] - ref["hist"]["r_pri"][-1])
+    dd = abs(rep["r_dual"][0] - ref["hist"]["r_dual"][-1])
+    step = {"b_vox": vox(b, ref["last"][0]), "z_vox": vox(z, ref["last"][1]),
+            "u_vox": vox(u, ref["last"][2]),
+            "r_pri_rel": dp / ref["hist"]["r_pri"][-1], "r_dual_rel": dd / ref["hist"]["r_dual"][-1],
+            "r_pri_over_scale": dp / scale, "r_dual_over_scale": dd / (RHO * P.v * scale)}
+    return {"trajectory": traj, "one_step_from_oracle_iterate": step,
+            "note": "tolerances: field 1e-3 voxel per step; histories 1e-4 relative or, near "
+                    "convergence where r_dual is a small difference of nearly equal fields, "
+                    "4e-5 of the scale max(|b|,|z|) (rho v times it for r_dual; 2e-6 in float32); "
+                    "whole trajectories at this size amplify float32 differences"}
 
 
 def engine_same_volumes(imgs, vols, m3, m2, M, steps, max_iter, iters_per_step=16):
@@ -330,7 +382,7 @@ def main():
     ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--volumes", type=int, default=4, help="distinct seeds, cycled over steps")
-    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--cpu-iters", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gn", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
@@ -431,6 +483,11 @@ def main():
         kernels[name] = {"avg_us": avg_ms * 1e3, "launches": cnt, "total_ms": ms,
                          "bytes_per_launch": nbytes[name],
                          "GB_s": round(gbs, 1) if gbs else None}
+        fl = mfma_flops(M, m2, m3, "mixed").get(name)
+        if fl:
+            tf = fl / (avg_ms * 1e-3) / 1e12
+            kernels[name].update({"mfma_flops_per_launch": fl, "mfma_TFLOP_s": round(tf, 1),
+                                  "mfma_frac_of_bf16_peak": round(tf / 2500.0, 4)})
     dom = max((k for k in kernels if nbytes[k]), key=lambda k: kernels[k]["total_ms"])
     peak = 8000.0
     ach = kernels[dom]["GB_s"]
@@ -475,9 +532,13 @@ def main():
         served = served_leg(dev, args.serve_seconds, args.serve_rate, args.serve_pool, MAX_ITER)
 
     base = None
+    err = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle sample")
-        base = cpu_baseline(vols[0], float(np.mean(iters)), args.cpu_iters)
+        base, ref = cpu_baseline(vols[0], float(np.mean(iters)), args.cpu_iters)
+        log(f"cpu baseline: {json.dumps(base)}")
+        err = oracle_error(probs[0], ref, args.cpu_iters, (m3, m2, M + 1))
+        log(f"error vs oracle: {json.dumps(err)}")
 
     for p in probs:
         p.close()
@@ -510,6 +571,7 @@ def main():
         "batched": batched,
         "served": served,
         "cpu_baseline": base,
+        "error_vs_oracle": err,
     }
     print(json.dumps(out), flush=True)
 
