@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define EPI_ABI_VERSION 1
+#define EPI_ABI_VERSION 2
 
 typedef enum {
   EPI_OK = 0,
@@ -106,24 +106,35 @@ typedef struct {
   int32_t *pcg_iters;
 } epi_gn_report;
 
+/* Penalty parameter strategy of ADMM (Section 4.3, the adaptive choice of rho by residual
+ * balancing): FIXED keeps rho; ADAPT multiplies rho by tau when the primal residual
+ * exceeds mu times the dual residual and divides it by tau in the opposite case;
+ * ADAPT_FLOOR does the same but skips a decrease that would take rho below rho_min. On a
+ * change the scaled dual u = y / (rho v) is rescaled by rho_old / rho_new (y unchanged). */
+enum { EPI_RHO_FIXED = 0, EPI_RHO_ADAPT = 1, EPI_RHO_ADAPT_FLOOR = 2 };
+
 /* ADMM options (Section 4.2). Defaults from epi_admm_default_opts: max_iter 100,
  * sqp_iters 1 (linearisations per b-step), check_every 8 (iterations between host polls
  * of the device-side stopping flag; results do not depend on it), rho 1e3,
- * eps_abs = eps_rel = 0.2 (eq. admmStop). */
+ * eps_abs = eps_rel = 0.2 (eq. admmStop), rho_mode EPI_RHO_FIXED, tau 1.3, mu 10,
+ * rho_min 1e2. */
 typedef struct {
   int32_t max_iter, sqp_iters, check_every;
   double rho, eps_abs, eps_rel;
+  int32_t rho_mode;
+  double tau, mu, rho_min;
 } epi_admm_opts;
 
 /* ADMM report. Host arrays of length max_iter owned by the caller (NULL allowed):
  * per-iteration primal residual |b - z|, dual residual rho v |z_k - z_k+1| and their
- * tolerances (eq. admmStop, newest iterates). max_active = largest number of active
- * constraints of one PE line at exit of any b-step; hard_lines = total count of
- * (iteration, line) pairs that needed more than the unconstrained step. */
+ * tolerances (eq. admmStop, newest iterates), and the rho each iteration used.
+ * max_active = largest number of active constraints of one PE line at exit of any
+ * b-step; hard_lines = total count of (iteration, line) pairs that needed more than the
+ * unconstrained step. */
 typedef struct {
   int32_t iters, converged, status, max_active;
   int64_t hard_lines;
-  double *r_pri, *r_dual, *eps_pri, *eps_dual;
+  double *r_pri, *r_dual, *eps_pri, *eps_dual, *rho;
 } epi_admm_report;
 
 /* Kernel families of one ADMM iteration, for epi_profile_admm. */

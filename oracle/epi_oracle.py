@@ -42,6 +42,7 @@ __all__ = [
     "pcg", "gn_direction", "armijo", "solve_gnpcg", "GNReport",
     "dct_matrix", "dct_eigs", "zstep", "qp_active_set", "bstep_line", "bstep",
     "admm_residuals", "solve_admm", "ADMMReport", "augmented_lagrangian",
+    "adapt_rho", "RHO_FIXED", "RHO_ADAPT", "RHO_ADAPT_FLOOR",
     "dense_operators",
 ]
 
@@ -693,14 +694,38 @@ class ADMMReport:
     eps_dual: List[float] = field(default_factory=list)
     max_active: List[int] = field(default_factory=list)
     lagrangian: List[float] = field(default_factory=list)
+    rho: List[float] = field(default_factory=list)
     iters: int = 0
     converged: bool = False
 
 
+RHO_FIXED, RHO_ADAPT, RHO_ADAPT_FLOOR = 0, 1, 2
+
+
+def adapt_rho(rho, r_pri, r_dual, mode, tau=1.3, mu=10.0, rho_min=1e2):
+    """Residual balancing (Section 4.3, adaptive penalty; Boyd et al. Section 3.4.1):
+    rho * tau if r_pri > mu r_dual, rho / tau if r_dual > mu r_pri, else unchanged. Mode
+    RHO_ADAPT_FLOOR skips a decrease that would go below rho_min. Returns the new rho; the
+    caller rescales the scaled dual u by rho_old / rho_new so that y = rho v u is unchanged."""
+    if mode == RHO_FIXED:
+        return rho
+    if r_pri > mu * r_dual:
+        return rho * tau
+    if r_dual > mu * r_pri:
+        new = rho / tau
+        if mode == RHO_ADAPT_FLOOR and new < rho_min:
+            return rho
+        return new
+    return rho
+
+
 def solve_admm(P: Problem, b0=None, z0=None, u0=None, rho=1e3, max_iter=100,
-               eps_abs=0.2, eps_rel=0.2, sqp_iters=1, with_lagrangian=False, tol=1e-12):
+               eps_abs=0.2, eps_rel=0.2, sqp_iters=1, with_lagrangian=False, tol=1e-12,
+               rho_mode=RHO_FIXED, tau=1.3, mu=10.0, rho_min=1e2):
     """Scaled ADMM of Section 4.2: b-step (SQP/active set per line), z-step (DCT solve),
-    u^{k+1} = u^k + b^{k+1} - z^{k+1}; stop by eq. admmStop or after max_iter."""
+    u^{k+1} = u^k + b^{k+1} - z^{k+1}; stop by eq. admmStop or after max_iter. With an
+    adaptive rho_mode the penalty is updated after each non-final iteration by
+    :func:`adapt_rho` and u rescaled accordingly."""
     b = np.zeros((P.L, P.M + 1)) if b0 is None else P.lines(b0).copy()
     z = b.copy() if z0 is None else P.lines(z0).copy()
     u = np.zeros_like(b) if u0 is None else P.lines(u0).copy()
@@ -718,6 +743,7 @@ def solve_admm(P: Problem, b0=None, z0=None, u0=None, rho=1e3, max_iter=100,
         rep.r_dual.append(rd)
         rep.eps_pri.append(ep)
         rep.eps_dual.append(ed)
+        rep.rho.append(rho)
         rep.max_active.append(int(nact.max()) if nact.size else 0)
         if with_lagrangian:
             rep.lagrangian.append(augmented_lagrangian(P, b, z, u, rho))
@@ -725,6 +751,10 @@ def solve_admm(P: Problem, b0=None, z0=None, u0=None, rho=1e3, max_iter=100,
         if rp <= ep and rd <= ed:
             rep.converged = True
             break
+        if k + 1 < max_iter:
+            new = adapt_rho(rho, rp, rd, rho_mode, tau, mu, rho_min)
+            u = u * (rho / new)
+            rho = new
     return P.vol(b), P.vol(z), P.vol(u), rep
 
 

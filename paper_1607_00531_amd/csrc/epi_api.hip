@@ -158,6 +158,10 @@ EPI_API void epi_admm_default_opts(epi_admm_opts* o) {
   o->sqp_iters = 1;
   o->check_every = 8;
   o->rho = 1e3;
+  o->rho_mode = EPI_RHO_FIXED;
+  o->tau = 1.3;
+  o->mu = 10.0;
+  o->rho_min = 1e2;
   o->eps_abs = 0.2;
   o->eps_rel = 0.2;
 }
@@ -629,12 +633,30 @@ static epi_status count_violations(epi_problem* p, const float* b, float thr, do
   return EPI_OK;
 }
 
+epi_status epi::validate_rho_opts(const epi_admm_opts* o) {
+  if (o->rho_mode < EPI_RHO_FIXED || o->rho_mode > EPI_RHO_ADAPT_FLOOR)
+    return fail(EPI_EINVAL, "unknown rho_mode %d", o->rho_mode);
+  if (o->rho_mode != EPI_RHO_FIXED && !(o->tau > 1.0 && o->mu >= 1.0 && o->rho_min > 0.0))
+    return fail(EPI_EINVAL, "adaptive rho needs tau > 1, mu >= 1, rho_min > 0");
+  return EPI_OK;
+}
+
+void epi::init_rho_state(DevState* h, const epi_admm_opts* o) {
+  h->u_scale = 1.0;
+  h->rho_mode = o->rho_mode;
+  h->tau = o->tau;
+  h->mu = o->mu;
+  h->rho_min = o->rho_min;
+}
+
 static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float* d_u,
                                   const epi_admm_opts* opts, epi_admm_report* rep) {
   if (!p || !d_b || !d_z || !d_u || !opts) return fail(EPI_EINVAL, "null argument");
   if (!(opts->rho > 0.0)) return fail(EPI_EINVAL, "rho must be > 0");
   if (opts->max_iter < 0 || opts->sqp_iters < 1 || opts->check_every < 1)
     return fail(EPI_EINVAL, "max_iter >= 0, sqp_iters >= 1, check_every >= 1 required");
+  epi_status vo = validate_rho_opts(opts);
+  if (vo != EPI_OK) return vo;
   enter(p);
   double viol = 0.0;
   epi_status s = count_violations(p, d_b, 1.0f + 1e-5f, &viol);
@@ -647,7 +669,7 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
   if (cap > p->hist_cap) {
     if (p->hist) HIPCHK(hipFree(p->hist));
     p->hist = nullptr;
-    HIPCHK(hipMalloc(&p->hist, (size_t)4 * cap * sizeof(double)));
+    HIPCHK(hipMalloc(&p->hist, (size_t)EPI_HIST_ROWS * cap * sizeof(double)));
     p->hist_cap = cap;
     free_graph(p);   // the finalize node holds the history pointer
   }
@@ -660,6 +682,7 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
   h->v = p->v;
   h->admm_max = opts->max_iter;
   h->admm_done = opts->max_iter == 0 ? 2 : 0;
+  init_rho_state(h, opts);
   HIPCHK(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->exec));
 
   const int chunk = opts->check_every;
@@ -711,8 +734,9 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
     rep->max_active = h->max_active;
     rep->hard_lines = h->hard_total;
     rep->status = h->numeric_bad ? EPI_ENUMERIC : EPI_OK;
-    double* outs[4] = {rep->r_pri, rep->r_dual, rep->eps_pri, rep->eps_dual};
-    for (int k = 0; k < 4; ++k)
+    double* outs[EPI_HIST_ROWS] = {rep->r_pri, rep->r_dual, rep->eps_pri, rep->eps_dual,
+                                   rep->rho};
+    for (int k = 0; k < EPI_HIST_ROWS; ++k)
       if (outs[k] && iters > 0)
         HIPCHK(hipMemcpy(outs[k], p->hist + (size_t)k * p->hist_cap, iters * sizeof(double),
                          hipMemcpyDeviceToHost));

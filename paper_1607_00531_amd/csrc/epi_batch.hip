@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_batch_bstep(BatchDev* bd, int cls) {
   DevState* st = S.st;
   if (st->admm_done) return;
   const int line = gl - T.first[k];
-  const bool hard = bstep_line_body<P>(S.la, (float)st->rho, S.b, S.z, S.u, S.w, line, true,
+  const bool hard = bstep_line_body<P>(S.la, (float)st->rho, (float)st->u_scale, S.b, S.z, S.u, S.w, line, true,
                                        &sbuf[wave][0][0], lane, &st->numeric_bad);
   if (hard && lane == 0) {
     const int idx = atomicAdd(&bd->hard_count[cls], 1);
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(64) void k_batch_hard(BatchDev* bd, int cls) {
   for (int h = blockIdx.x; h < nh; h += gridDim.x) {
     const HardItem it = bd->hard_list[cls][h];
     const BatchSlotDev& S = bd->slots[it.slot];
-    hard_line_body<P>(S.la, (float)S.st->rho, S.b, S.z, S.u, S.w, it.line, L, threadIdx.x,
+    hard_line_body<P>(S.la, (float)S.st->rho, (float)S.st->u_scale, S.b, S.z, S.u, S.w, it.line, L, threadIdx.x,
                       &S.st->max_active);
   }
 }
@@ -334,6 +334,10 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
   if (vs != EPI_OK) return vs;
   if (!(opts->rho > 0.0) || opts->max_iter < 1 || opts->sqp_iters != 1)
     return fail(EPI_EINVAL, "batched ADMM needs rho > 0, max_iter >= 1, sqp_iters = 1");
+  {
+    epi_status vo = validate_rho_opts(opts);
+    if (vo != EPI_OK) return vo;
+  }
   const int64_t fp = epi_batch_footprint(grid, opts->max_iter);
   int sid = -1;
   for (int i = 0; i < bt->max_slots; ++i)
@@ -376,7 +380,7 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
   const long long tiles = std::max(tiles_axis3(s.M, s.m2), tiles_axis2(s.M, s.m3));
   const size_t part = (size_t)std::max<long long>(tiles * NQ_ADMM_E, 4096);
   if (hipMalloc(&s.partial, part * sizeof(double)) != hipSuccess ||
-      hipMalloc(&s.hist, (size_t)4 * s.hist_len * sizeof(double)) != hipSuccess)
+      hipMalloc(&s.hist, (size_t)EPI_HIST_ROWS * s.hist_len * sizeof(double)) != hipSuccess)
     return undo(fail(EPI_ENOMEM, "slot buffers"));
   epi_status ts = build_dct_tables(s.m2, s.m3, grid->h[1], grid->h[2], bt->precision, &s.tab);
   if (ts != EPI_OK) return undo(ts);
@@ -407,6 +411,7 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
   hst->sqrt_n = sqrt((double)s.n);
   hst->v = grid->h[0] * grid->h[1] * grid->h[2];
   hst->admm_max = opts->max_iter;
+  init_rho_state(hst, opts);
   if (hipMemcpy(dst, hst, sizeof(DevState), hipMemcpyHostToDevice) != hipSuccess)
     return undo(fail(EPI_EHIP, "state init"));
   batch_leave(bt);
@@ -592,8 +597,8 @@ EPI_API epi_status epi_batch_poll(epi_batch* bt, int32_t slot, int32_t* finished
   rep->max_active = h.max_active;
   rep->hard_lines = h.hard_total;
   rep->status = h.numeric_bad ? EPI_ENUMERIC : EPI_OK;
-  double* outs[4] = {rep->r_pri, rep->r_dual, rep->eps_pri, rep->eps_dual};
-  for (int k = 0; k < 4; ++k)
+  double* outs[EPI_HIST_ROWS] = {rep->r_pri, rep->r_dual, rep->eps_pri, rep->eps_dual, rep->rho};
+  for (int k = 0; k < EPI_HIST_ROWS; ++k)
     if (outs[k] && iters > 0)
       BHIPCHK(hipMemcpy(outs[k], s.hist + (size_t)k * s.hist_len,
                         std::min(iters, s.hist_len) * sizeof(double), hipMemcpyDeviceToHost));

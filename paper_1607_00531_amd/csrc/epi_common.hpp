@@ -41,6 +41,10 @@ struct DevState {
   int max_active, pad3;
   long long hard_total;
   int numeric_bad, pad4;
+  // residual balancing of rho (rho_mode 1, 2): u holds values scaled by u_scale until the
+  // next iteration has read it (the rescale rho_old / rho_new of the scaled dual)
+  double u_scale, tau, mu, rho_min;
+  int rho_mode, pad5;
 };
 
 // Number of float64 partial sums written per workgroup by each reduction kernel.

@@ -92,6 +92,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const float* T,
     // U rows per thread in flight: all their loads are issued before the first store
     // (the stores to z and u could alias the loads as far as the compiler knows)
     constexpr int U = 8;
+    const float us = (float)g.st->u_scale;   // pending rescale of u (1 with a fixed rho)
     const float* bb0 = g.b + bofs + c0;
     float* zb0 = g.z + bofs + c0;
     float* ub0 = g.u + bofs + c0;
@@ -103,7 +104,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const float* T,
         const size_t ro = (size_t)(row < g.rows ? row : 0) * g.ld;
         const bool ok = cok && row < g.rows;
         zo[q] = ok ? ld_at<float>(zb0 + ro, col4) : 0.0f;
-        uo[q] = ok ? ld_at<float>(ub0 + ro, col4) : 0.0f;
+        uo[q] = ok ? ld_at<float>(ub0 + ro, col4) * us : 0.0f;
         bb[q] = ok ? ld_at<float>(bb0 + ro, col4) : 0.0f;
       }
 #pragma unroll

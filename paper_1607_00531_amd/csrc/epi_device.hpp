@@ -108,6 +108,7 @@ __device__ __forceinline__ void admm_finalize(DevState* st, const double* sums, 
     hist[hist_len + it] = rdual;
     hist[2 * hist_len + it] = epri;
     hist[3 * hist_len + it] = edual;
+    hist[4 * hist_len + it] = rho;
   }
   st->admm_iter = it + 1;
   st->hard_total += st->hard_count;
@@ -120,6 +121,23 @@ __device__ __forceinline__ void admm_finalize(DevState* st, const double* sums, 
     st->admm_done = 1;
   } else if (st->admm_iter >= st->admm_max) {
     st->admm_done = 2;   // iteration cap: later launches of this solve are no-ops
+  }
+  // Residual balancing for the next iteration: rho * tau when the primal residual exceeds
+  // mu times the dual one, rho / tau in the opposite case (mode 2: not below rho_min);
+  // the scaled dual u = y / (rho v) is rescaled by rho_old / rho_new.
+  st->u_scale = 1.0;
+  if (!st->admm_done && st->rho_mode != 0) {
+    double rn = rho;
+    if (rpri > st->mu * rdual) {
+      rn = rho * st->tau;
+    } else if (rdual > st->mu * rpri) {
+      rn = rho / st->tau;
+      if (st->rho_mode == 2 && rn < st->rho_min) rn = rho;
+    }
+    if (rn != rho) {
+      st->u_scale = rho / rn;
+      st->rho = rn;
+    }
   }
 }
 // Workgroups are dealt round-robin over the 8 XCDs; remap so that each XCD (and its L2)

@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
-  const bool hard = bstep_line_body<P>(a, (float)st->rho, bvec, zvec, uvec, wvec,
+  const bool hard = bstep_line_body<P>(a, (float)st->rho, (float)st->u_scale, bvec, zvec, uvec, wvec,
                                        valid ? line : 0, valid, &sbuf[wave][0][0], lane,
                                        &st->numeric_bad);
   if (valid && hard && lane == 0) {
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __res
   if ((int)blockIdx.x >= nhard) return;
   __shared__ HardLds<P> L;
   for (int h = blockIdx.x; h < nhard; h += gridDim.x)
-    hard_line_body<P>(a, (float)st->rho, bvec, zvec, uvec, wvec, hard_list[h], L, threadIdx.x,
+    hard_line_body<P>(a, (float)st->rho, (float)st->u_scale, bvec, zvec, uvec, wvec, hard_list[h], L, threadIdx.x,
                       &st->max_active);
 }
 

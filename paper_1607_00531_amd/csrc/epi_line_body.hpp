@@ -132,7 +132,7 @@ __device__ __forceinline__ void qp_data(const LineArgs& a, float rho, const floa
 // place) and w = b^{k+1} + u^k. sw: this wave's five LDS line buffers. Every wave of the
 // workgroup must call it (barriers).
 template <int P>
-__device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho,
+__device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho, float us,
                                                 float* __restrict__ bvec,
                                                 const float* __restrict__ zvec,
                                                 const float* __restrict__ uvec,
@@ -152,7 +152,7 @@ __device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho,
   for (int j = 0; j < P; ++j) {
     b[j] = v[2][j];
     z[j] = v[3][j];
-    u[j] = v[4][j];
+    u[j] = v[4][j] * us;   // pending rescale of the scaled dual (1 with a fixed rho)
   }
   float Gd[P], Go[P], c[P], g[P];
   qp_data<P>(a, rho, b, z, u, sIp, sIm, lane, Gd, Go, c, g);
@@ -324,7 +324,7 @@ struct HardLds {
 };
 
 template <int P>
-__device__ __forceinline__ void hard_line_body(const LineArgs& a, float rho,
+__device__ __forceinline__ void hard_line_body(const LineArgs& a, float rho, float us,
                                                float* __restrict__ bvec,
                                                const float* __restrict__ zvec,
                                                const float* __restrict__ uvec,
@@ -340,6 +340,8 @@ __device__ __forceinline__ void hard_line_body(const LineArgs& a, float rho,
   stage_in<P>(bvec + base, NF, true, L.stg, b, lane);
   stage_in<P>(zvec + base, NF, true, L.stg, z, lane);
   stage_in<P>(uvec + base, NF, true, L.stg, u, lane);
+#pragma unroll
+  for (int j = 0; j < P; ++j) u[j] *= us;
   float Gdr[P], Gor[P], cr[P], gr[P];
   qp_data<P>(a, rho, b, z, u, L.sIp, L.sIm, lane, Gdr, Gor, cr, gr);
 #pragma unroll

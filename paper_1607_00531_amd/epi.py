@@ -52,16 +52,24 @@ class GNReport(C.Structure):
                 ("step", C.POINTER(C.c_double)), ("pcg_iters", C.POINTER(C.c_int32))]
 
 
+# penalty strategies of epi_admm_opts.rho_mode
+RHO_MODES = {"fixed": 0, "adapt": 1, "adapt_floor": 2}
+ABI_VERSION = 2
+
+
 class ADMMOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("sqp_iters", C.c_int32), ("check_every", C.c_int32),
-                ("rho", C.c_double), ("eps_abs", C.c_double), ("eps_rel", C.c_double)]
+                ("rho", C.c_double), ("eps_abs", C.c_double), ("eps_rel", C.c_double),
+                ("rho_mode", C.c_int32), ("tau", C.c_double), ("mu", C.c_double),
+                ("rho_min", C.c_double)]
 
 
 class ADMMReport(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("status", C.c_int32),
                 ("max_active", C.c_int32), ("hard_lines", C.c_int64),
                 ("r_pri", C.POINTER(C.c_double)), ("r_dual", C.POINTER(C.c_double)),
-                ("eps_pri", C.POINTER(C.c_double)), ("eps_dual", C.POINTER(C.c_double))]
+                ("eps_pri", C.POINTER(C.c_double)), ("eps_dual", C.POINTER(C.c_double)),
+                ("rho", C.POINTER(C.c_double))]
 
 
 class KernelProfile(C.Structure):
@@ -86,6 +94,9 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, st = C.c_void_p, C.c_int
         L.epi_abi_version.restype = C.c_int32
+        if L.epi_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {L.epi_abi_version()}, "
+                              f"this binding expects {ABI_VERSION}: rebuild the library")
         L.epi_last_error.restype = C.c_char_p
         L.epi_setup.argtypes = [C.POINTER(Grid), vp, vp, vp, C.POINTER(vp)]
         L.epi_setup.restype = st
@@ -261,9 +272,9 @@ class Problem:
         o = ADMMOpts()
         lib().epi_admm_default_opts(C.byref(o))
         for k, v in kw.items():
-            setattr(o, k, v)
+            setattr(o, k, RHO_MODES[v] if k == "rho_mode" and isinstance(v, str) else v)
         n1 = max(o.max_iter, 1)
-        arrs = {k: (C.c_double * n1)() for k in ("r_pri", "r_dual", "eps_pri", "eps_dual")}
+        arrs = {k: (C.c_double * n1)() for k in ("r_pri", "r_dual", "eps_pri", "eps_dual", "rho")}
         rep = ADMMReport()
         for k, a in arrs.items():
             setattr(rep, k, C.cast(a, C.POINTER(C.c_double)))
@@ -352,7 +363,7 @@ class Batch:
         o = ADMMOpts()
         L.epi_admm_default_opts(C.byref(o))
         for k, v in opts.items():
-            setattr(o, k, v)
+            setattr(o, k, RHO_MODES[v] if k == "rho_mode" and isinstance(v, str) else v)
         slot = C.c_int32(-1)
         st = L.epi_batch_admit(self._h, C.byref(g), _ptr(Ip), _ptr(Im), _ptr(b), _ptr(z),
                                _ptr(u), C.byref(o), C.byref(slot))
@@ -376,7 +387,7 @@ class Batch:
         if not fin.value:
             return None
         n1 = self._maxit[slot]
-        arrs = {k: (C.c_double * n1)() for k in ("r_pri", "r_dual", "eps_pri", "eps_dual")}
+        arrs = {k: (C.c_double * n1)() for k in ("r_pri", "r_dual", "eps_pri", "eps_dual", "rho")}
         rep = ADMMReport()
         for k, a in arrs.items():
             setattr(rep, k, C.cast(a, C.POINTER(C.c_double)))

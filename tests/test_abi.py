@@ -29,7 +29,10 @@ def test_library_exports_every_declared_symbol():
     lib = epi.lib()
     for n in declared_functions():
         assert hasattr(lib, n), n
-    assert lib.epi_abi_version() == 1
+    import re
+    hdr = open(os.path.join(ROOT, "include", "epi.h")).read()
+    declared = int(re.search(r"#define EPI_ABI_VERSION (\d+)", hdr).group(1))
+    assert lib.epi_abi_version() == declared == epi.ABI_VERSION
 
 
 def test_default_options_are_the_papers():
@@ -39,6 +42,8 @@ def test_default_options_are_the_papers():
     assert g["eta"] == 0.1 and g["eps_obj"] == 1e-3 and g["eps_iter"] == 1e-2 and g["eps_grad"] == 1e-2
     a = admm_default_opts()
     assert a["eps_abs"] == 0.2 and a["eps_rel"] == 0.2 and a["sqp_iters"] == 1
+    # adaptive penalty constants (tau, mu, rho_min of the paper's 3D experiments)
+    assert a["rho_mode"] == 0 and a["tau"] == 1.3 and a["mu"] == 10.0 and a["rho_min"] == 1e2
 
 
 def test_ctypes_structs_match_header_field_order():

@@ -151,3 +151,39 @@ def test_active_set_lines_in_a_batch():
         assert rep["hard_lines"] > 0 and rep["max_active"] == int(nact.max())
         for gpu, cpu in zip(st, (bn, zn, un)):
             assert np.abs(N(gpu).reshape(P.L, -1) - cpu).max() / P.hp <= FIELD_VOX
+
+
+def test_adaptive_rho_in_a_batch():
+    """Slots with different penalty strategies side by side: every slot's result is the same
+    as alone (bitwise) and its rho history equals the single-volume solver's."""
+    from paper_1607_00531_amd import Problem
+    items = [(0, (generate(20, (30, 26, 10), 0), 5.0), dict(rho=1e5, rho_mode="adapt")),
+             (1, (generate(21, (48, 44), 1), 50.0), dict(rho=1e6, rho_mode="adapt_floor")),
+             (2, (generate(22, (24, 20, 14), 0), 5.0), dict(rho=1e3, rho_mode="fixed"))]
+    common = dict(max_iter=24, eps_abs=0.0, eps_rel=0.0)
+    from paper_1607_00531_amd import Batch
+
+    def run(sel):
+        out = {}
+        with Batch(max_slots=4, precision="mixed", iters_per_step=5) as bt:
+            slots = {}
+            for key, (v, alpha), o in sel:
+                st = _state(v)
+                slots[bt.admit(T(v.Ip), T(v.Im), v.h, alpha, *st, **o, **common)] = (key, st)
+            while bt.step() > 0:
+                pass
+            for s, (key, st) in slots.items():
+                out[key] = (bt.poll(s), [N(x) for x in st])
+        return out
+
+    mix = run(items)
+    for it in items:
+        alone = run([it])[it[0]]
+        assert alone[0]["rho"] == mix[it[0]][0]["rho"]
+        for a, b in zip(alone[1], mix[it[0]][1]):
+            np.testing.assert_array_equal(a, b)
+        (v, alpha), o = it[1], it[2]
+        with Problem(T(v.Ip), T(v.Im), v.h, alpha, precision="mixed") as pr:
+            st = _state(v)
+            rep = pr.solve_admm(*st, **o, **common)
+        assert rep["rho"] == mix[it[0]][0]["rho"]

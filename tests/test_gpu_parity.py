@@ -289,3 +289,42 @@ def test_deterministic():
             outs.append((N(b), N(z), N(bg), r1["r_pri"], r2["J"]))
     for a, c in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(np.asarray(a), np.asarray(c))
+
+
+# ---------------------------------------------------------------------------------------
+# Adaptive penalty (residual balancing, Section 4.3)
+# ---------------------------------------------------------------------------------------
+def _rho_decisions_not_borderline(ro, mu=10.0, margin=1e-3):
+    """The comparison is well posed only if no oracle decision sits on a threshold."""
+    for rp, rd in zip(ro.r_pri, ro.r_dual):
+        assert abs(rp / (mu * rd) - 1.0) > margin and abs(rd / (mu * rp) - 1.0) > margin
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("shape,pe,alpha,rho0,mode,iters", [
+    ((64, 64), 1, 50.0, 1e6, "adapt_floor", 40),
+    ((20, 24, 12), 1, 0.5, 10.0, "adapt", 20),
+    ((30, 26, 10), 0, 5.0, 1e5, "adapt", 30)])
+def test_admm_adaptive_rho_trajectory(shape, pe, alpha, rho0, mode, iters, prec):
+    v = generate(0, shape, pe)
+    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
+    mid = {"adapt": O.RHO_ADAPT, "adapt_floor": O.RHO_ADAPT_FLOOR}[mode]
+    bo, zo, uo, ro = O.solve_admm(P, rho=rho0, max_iter=iters, eps_abs=0.0, eps_rel=0.0,
+                                  rho_mode=mid)
+    assert len(set(ro.rho)) > 2
+    _rho_decisions_not_borderline(ro)
+    with _problem(v, alpha, prec) as pr:
+        b = T(np.zeros(pr.shape_faces))
+        z, u = b.clone(), b.clone()
+        rep = pr.solve_admm(b, z, u, rho=rho0, max_iter=iters, eps_abs=0.0, eps_rel=0.0,
+                            rho_mode=mode, check_every=7)
+        assert rep["rho"] == ro.rho
+        for gpu, cpu in ((b, bo), (z, zo), (u, uo)):
+            err = np.abs(N(gpu) - cpu).max() / P.hp
+            assert err <= FIELD_VOX, err
+        scale = max(np.linalg.norm(bo), np.linalg.norm(zo))
+        ok, msg = hist_ok(rep["r_pri"], ro.r_pri, scale, prec)
+        assert ok, ("r_pri", msg)
+        for k, (a, c, rk) in enumerate(zip(rep["r_dual"], ro.r_dual, ro.rho)):
+            ok, msg = hist_ok([a], [c], scale * rk * P.v, prec)
+            assert ok, ("r_dual", k, msg)

@@ -432,3 +432,68 @@ def test_2d_is_3d_with_one_slice():
     bA, _ = O.solve_gnpcg(P2, max_iter=3, use_stopping=False)
     bB, _ = O.solve_gnpcg(P3, max_iter=3, use_stopping=False)
     np.testing.assert_allclose(bA, bB, rtol=1e-6, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------------------
+# Adaptive penalty (Section 4.3, closing paragraph: Boyd's residual balancing, optionally
+# bounded below by rho_min) and the rescale of the scaled dual
+# ---------------------------------------------------------------------------------------
+def _fig7_rho(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    return np.loadtxt(path)[:, 1]
+
+
+def test_adapt_rho_rule_cases():
+    A, F = O.RHO_ADAPT, O.RHO_ADAPT_FLOOR
+    assert O.adapt_rho(1e3, 11.0, 1.0, A) == 1e3 * 1.3          # primal residual dominates
+    assert O.adapt_rho(1e3, 1.0, 11.0, A) == 1e3 / 1.3          # dual residual dominates
+    assert O.adapt_rho(1e3, 9.0, 1.0, A) == 1e3                 # within the band mu = 10
+    assert O.adapt_rho(1e3, 11.0, 1.0, O.RHO_FIXED) == 1e3
+    assert O.adapt_rho(120.0, 1.0, 11.0, F) == 120.0            # 120 / 1.3 < 100: skipped
+    assert O.adapt_rho(140.0, 1.0, 11.0, F) == 140.0 / 1.3
+    assert O.adapt_rho(120.0, 1.0, 11.0, A) == 120.0 / 1.3      # no bound without the floor
+
+
+@pytest.mark.parametrize("name,mode", [("fig7_rho_adaptive.txt", O.RHO_ADAPT),
+                                       ("fig7_rho_adaptive_bounded.txt", O.RHO_ADAPT_FLOOR)])
+def test_adaptive_rho_reproduces_figure7(name, mode):
+    """On the coarsest level of Figure 7 every iteration asks for a decrease. From
+    rho^0 = 1e6 the rule reproduces the printed sequences: divisions by tau = 1.3, and with
+    rho_min = 1e2 the decrease that would go below the bound is skipped, so rho stays at
+    1e6 / 1.3^35 = 102.7975... (clamping to the bound would give 100)."""
+    ref = _fig7_rho(name)
+    rho, seq = 1e6, []
+    for _ in range(len(ref)):
+        seq.append(rho)
+        rho = O.adapt_rho(rho, 1.0, 100.0, mode, tau=1.3, mu=10.0, rho_min=1e2)
+    np.testing.assert_allclose(seq, ref, rtol=1e-12)
+
+
+def test_adaptive_admm_equals_the_unscaled_iteration():
+    """The scaled iteration (eq. admmStep1-3) with u rescaled by rho_old / rho_new at every
+    change of rho is the unscaled iteration (eq. UadmmStep1-3) in y = rho v u, which keeps y
+    across a change of rho: b and z agree and u^k = y^k / (rho_k v) throughout."""
+    from synth import generate
+    v = generate(1, (20, 24, 12), 1)
+    P = O.make_problem(v.Ip, v.Im, v.h, 0.5)
+    its = 14
+    b, z, u, rep = O.solve_admm(P, rho=10.0, max_iter=its, eps_abs=0.0, eps_rel=0.0,
+                                rho_mode=O.RHO_ADAPT)
+    assert len(set(rep.rho)) > 3                       # rho changed several times
+    bb = np.zeros((P.L, P.M + 1))
+    zz, y, rho = bb.copy(), bb.copy(), 10.0
+    for k in range(its):
+        assert rho == rep.rho[k]
+        uk = y / (rho * P.v)                           # the b- and z-steps of eq. UadmmStep
+        bb, _, _ = O.bstep(P, bb, zz, uk, rho)
+        zn = O.zstep(P, bb + uk, rho)
+        y = y + rho * P.v * (bb - zn)
+        rp = np.linalg.norm(bb - zn)
+        rd = rho * P.v * np.linalg.norm(zn - zz)
+        zz = zn
+        if k + 1 < its:
+            rho = O.adapt_rho(rho, rp, rd, O.RHO_ADAPT)
+    np.testing.assert_allclose(bb, P.lines(b), rtol=0, atol=1e-12 * np.abs(bb).max())
+    np.testing.assert_allclose(zz, P.lines(z), rtol=0, atol=1e-12 * np.abs(zz).max())
+    np.testing.assert_allclose(y / (rho * P.v), P.lines(u), rtol=0,
+                               atol=1e-10 * np.abs(P.lines(u)).max())
