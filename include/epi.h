@@ -172,6 +172,20 @@ void epi_admm_default_opts(epi_admm_opts* opts);
 epi_status epi_setup(const epi_grid* grid, const float* d_Iplus, const float* d_Iminus,
                      void* stream, epi_problem** out);
 
+/* Quality of a field estimate: the SSD distance D of the corrected pair (eq. D), the
+ * normalised cross-correlation of the two corrected images and their means. */
+typedef struct {
+  double D, ncc, mean_plus, mean_minus;
+} epi_quality;
+
+/* Distortion-corrected images at the field d_b (n floats): I_v(x + A b)(1 + D1 b) into
+ * d_Iplus_corr and I_-v(x - A b)(1 - D1 b) into d_Iminus_corr, N floats each in canonical
+ * cell layout, caller-owned (both NULL: quality only; one NULL: EPI_EINVAL). They follow
+ * the model relation of Section 2 (eq. (1)) as discretised in Section 3; at an exact field
+ * they coincide with the undistorted image. Synchronises the stream. */
+epi_status epi_corrected_images(epi_problem* p, const float* d_b, float* d_Iplus_corr,
+                                float* d_Iminus_corr, epi_quality* out);
+
 /* Evaluate the objective terms at d_b (n floats): D, S and, if with_penalty != 0, P
  * (eq. D, eq. S, eq. P). If d_grad is not NULL it receives grad J (with_penalty = 0) or
  * grad J_GN (with_penalty != 0), n floats (eq. dJ, eq. dJGN). Synchronises the stream. */

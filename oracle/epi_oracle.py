@@ -43,6 +43,7 @@ __all__ = [
     "dct_matrix", "dct_eigs", "zstep", "qp_active_set", "bstep_line", "bstep",
     "admm_residuals", "solve_admm", "ADMMReport", "augmented_lagrangian",
     "adapt_rho", "RHO_FIXED", "RHO_ADAPT", "RHO_ADAPT_FLOOR",
+    "corrected_images", "ncc", "image_quality",
     "dense_operators",
 ]
 
@@ -141,6 +142,29 @@ def line_eval(P: Problem, b: np.ndarray) -> Dict[str, np.ndarray]:
     Tv = ipv + imv
     return dict(a=a, g=g, r=r, Jl=0.5 * Sd - Tv / P.hp, Jr=0.5 * Sd + Tv / P.hp,
                 ipv=ipv, imv=imv, ipd=ipd, imd=imd)
+
+
+def corrected_images(P: Problem, b):
+    """The two distortion-corrected images of the model relation (Section 2, eq. (1) and
+    its discretisation eq. D): I+(x + A b)(1 + D1 b) and I-(x - A b)(1 - D1 b) at the cell
+    centres, each (L, M). They coincide at a perfect field; r is their difference."""
+    e = line_eval(P, b)
+    return e["ipv"] * (1.0 + e["g"]), e["imv"] * (1.0 - e["g"])
+
+
+def ncc(x, y) -> float:
+    """Normalised cross-correlation of two images (sums over all cells)."""
+    x = np.asarray(x, np.float64).ravel()
+    y = np.asarray(y, np.float64).ravel()
+    xc, yc = x - x.mean(), y - y.mean()
+    return float(np.dot(xc, yc) / math.sqrt(np.dot(xc, xc) * np.dot(yc, yc)))
+
+
+def image_quality(P: Problem, b) -> Dict[str, float]:
+    """SSD distance D(b) = (v/2)|I+corr - I-corr|^2 and the NCC of the corrected pair."""
+    cp, cm = corrected_images(P, b)
+    return dict(D=0.5 * P.v * float(np.sum((cp - cm) ** 2)), ncc=ncc(cp, cm),
+                mean_plus=float(cp.mean()), mean_minus=float(cm.mean()))
 
 
 def distance(P: Problem, b) -> float:

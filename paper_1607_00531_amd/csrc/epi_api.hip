@@ -454,6 +454,35 @@ static void terms_from_state(const epi_problem* p, const DevState* s, int with_p
   t->J = t->D + p->grid.alpha * t->S + t->P;
 }
 
+EPI_API epi_status epi_corrected_images(epi_problem* p, const float* d_b, float* d_Iplus_corr,
+                                        float* d_Iminus_corr, epi_quality* out) {
+  if (!p || !d_b || !out) return fail(EPI_EINVAL, "null argument");
+  if ((d_Iplus_corr == nullptr) != (d_Iminus_corr == nullptr))
+    return fail(EPI_EINVAL, "give both corrected-image buffers or neither");
+  enter(p);
+  launch_correct(p->exec, p->P, p->la, d_b, d_Iplus_corr, d_Iminus_corr, p->partial);
+  CHKLAUNCH();
+  FinArgs f{};
+  f.kind = FIN_QUALITY;
+  f.partial = p->partial;
+  f.nb1 = line_blocks(p->la);
+  launch_finalize(p->exec, f, p->st);
+  CHKLAUNCH();
+  HIPCHK(hipMemcpyAsync(p->st_h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+  HIPCHK(hipStreamSynchronize(p->exec));
+  leave(p);
+  const double* q = p->st_h->quality;
+  const double n = (double)p->N;
+  const double mp = q[0] / n, mm = q[1] / n;
+  const double vp = q[2] - n * mp * mp, vm = q[3] - n * mm * mm, cov = q[4] - n * mp * mm;
+  out->D = 0.5 * p->v * q[5];
+  out->ncc = (vp > 0.0 && vm > 0.0) ? cov / sqrt(vp * vm) : 0.0;
+  out->mean_plus = mp;
+  out->mean_minus = mm;
+  if (!(out->D == out->D)) return fail(EPI_ENUMERIC, "corrected images are not finite");
+  return EPI_OK;
+}
+
 EPI_API epi_status epi_objective(epi_problem* p, const float* d_b, int32_t with_penalty,
                                     epi_terms* out, float* d_grad) {
   if (!p || !d_b || !out) return fail(EPI_EINVAL, "null argument");

@@ -45,13 +45,16 @@ struct DevState {
   // next iteration has read it (the rescale rho_old / rho_new of the scaled dual)
   double u_scale, tau, mu, rho_min;
   int rho_mode, pad5;
+  // corrected-image pair: sum a, sum b, sum a^2, sum b^2, sum ab, sum (a - b)^2
+  double quality[6];
 };
 
 // Number of float64 partial sums written per workgroup by each reduction kernel.
 enum : int {
   NQ_EVAL = 6,    // sum r^2, sum g^2, sum cross diffs^2, sum phi, infeasible count, |grad|^2
   NQ_PCG = 2,     // two dot products
-  NQ_ADMM_E = 5   // |b-z|^2, |z-z_old|^2, |z|^2, |u|^2, |b|^2
+  NQ_ADMM_E = 5,  // |b-z|^2, |z-z_old|^2, |z|^2, |u|^2, |b|^2
+  NQ_QUALITY = 6  // sums of the corrected-image pair
 };
 
 // Arguments of the DCT products of the z-step.

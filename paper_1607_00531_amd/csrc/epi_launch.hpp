@@ -28,6 +28,8 @@ void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* 
 
 // epi_vec.hip
 int flat_blocks(long long n);
+void launch_correct(hipStream_t s, int P, LineArgs a, const float* b, float* outp, float* outm,
+                    double* partial);
 void launch_matvec(hipStream_t s, LineArgs a, const float* p, const float* hdiag,
                    const float* hoff, float* q, double* partial, const DevState* st);
 void launch_pupdate(hipStream_t s, long long n, const float* z, float* p, const DevState* st);
@@ -49,7 +51,8 @@ enum FinKind : int {
   FIN_STEP = 6,        // |lam d|^2, |b_old|^2
   FIN_ADMM = 7,        // residuals, tolerances, stopping flag, history
   FIN_LS_INIT = 8,     // J0 = value; clear the line-search state
-  FIN_HARD_RESET = 9   // fold hard_count into hard_total between SQP linearisations
+  FIN_HARD_RESET = 9,  // fold hard_count into hard_total between SQP linearisations
+  FIN_QUALITY = 10     // -> st->quality (sums of the corrected-image pair)
 };
 struct FinArgs {
   int kind;
@@ -61,7 +64,7 @@ struct FinArgs {
   const double* partial3;
   int trial;
   double v, alpha, beta;
-  double* hist;      // ADMM history base (4 arrays of hist_len)
+  double* hist;      // ADMM history base (EPI_HIST_ROWS arrays of hist_len)
   int hist_len;
   double value;
 };

@@ -291,6 +291,58 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
   }
 }
 
+// Distortion-corrected images (Section 2, the model relation behind eq. D):
+// I+(x + A b)(1 + D1 b) and I-(x - A b)(1 - D1 b) at the cell centres of each line, and
+// float64 sums of the pair for the SSD and NCC quality measures. outp / outm may be null.
+template <int P>
+__global__ __launch_bounds__(256) void k_correct(LineArgs a, const float* __restrict__ bsrc,
+                                                 float* __restrict__ outp,
+                                                 float* __restrict__ outm, double* partial) {
+  __shared__ float sbuf[EPI_LINE_WAVES][4][LineBuf<P>::SIZE];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int line = xcd_remap(blockIdx.x, a.nblk) * EPI_LINE_WAVES + wave;
+  const bool valid = line < a.L;
+  const int lc = valid ? line : 0;
+  const int NF = a.M + 1;
+  const float* srcs[3] = {a.Ip + (size_t)lc * a.M, a.Im + (size_t)lc * a.M,
+                          bsrc + (size_t)lc * NF};
+  const int cnt[3] = {a.M, a.M, NF};
+  float v[3][P];
+  stage_in_n<P, 3>(srcs, cnt, valid, &sbuf[wave][0][0], v, lane);
+  const float* sIp = sbuf[wave][0];
+  const float* sIm = sbuf[wave][1];
+  const float bnext = shfl_down0(v[2][0], 1, lane);
+  float ov[2][P];
+  double acc[NQ_QUALITY] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int c = P * lane + j;
+    const float bl = v[2][j], br = (j < P - 1) ? v[2][j + 1] : bnext;
+    const float aidx = 0.5f * (bl + br) * a.inv_hp;
+    const float g = (br - bl) * a.inv_hp;
+    float ipv, ipd, imv, imd;
+    interp_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
+    interp_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
+    const bool in = valid && c < a.M;
+    const float cp = in ? ipv * (1.0f + g) : 0.0f;
+    const float cm = in ? imv * (1.0f - g) : 0.0f;
+    ov[0][j] = cp;
+    ov[1][j] = cm;
+    const double dp = cp, dm = cm;
+    acc[0] += dp;
+    acc[1] += dm;
+    acc[2] += dp * dp;
+    acc[3] += dm * dm;
+    acc[4] += dp * dm;
+    acc[5] += (dp - dm) * (dp - dm);
+  }
+  const bool store = valid && outp != nullptr && outm != nullptr;
+  float* outs[2] = {store ? outp + (size_t)lc * a.M : nullptr,
+                    store ? outm + (size_t)lc * a.M : nullptr};
+  stage_out_n<P, 2>(outs, a.M, store, &sbuf[wave][2][0], ov, lane);
+  block_partials<NQ_QUALITY>(acc, partial, blockIdx.x);
+}
+
 // Hard lines of the b-step: one wavefront per line (see hard_line_body).
 template <int P>
 __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __restrict__ bvec,
@@ -356,6 +408,13 @@ void launch_pcg_update(hipStream_t s, int P, LineArgs a, int precond, const floa
   const int nb = line_blocks(a);
   EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_pcg_update<PP>), dim3(nb), dim3(256), 0, s, a,
                                        precond, hdiag, hoff, x, r, z, p, q, partial, st));
+}
+
+void launch_correct(hipStream_t s, int P, LineArgs a, const float* b, float* outp, float* outm,
+                    double* partial) {
+  const int nb = line_blocks(a);
+  EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_correct<PP>), dim3(nb), dim3(256), 0, s, a, b, outp,
+                                       outm, partial));
 }
 
 void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* z,

@@ -227,6 +227,10 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f, DevState* st) {
         st->J_acc = f.value;
       }
     } break;
+    case FIN_QUALITY: {
+      reduce_partials<NQ_QUALITY>(f.partial, f.nb1, s);
+      if (threadIdx.x < NQ_QUALITY) st->quality[threadIdx.x] = s[threadIdx.x];
+    } break;
     case FIN_HARD_RESET: {
       if (threadIdx.x == 0 && !st->admm_done) {
         st->hard_total += st->hard_count;

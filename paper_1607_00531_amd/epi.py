@@ -72,6 +72,11 @@ class ADMMReport(C.Structure):
                 ("rho", C.POINTER(C.c_double))]
 
 
+class Quality(C.Structure):
+    _fields_ = [("D", C.c_double), ("ncc", C.c_double), ("mean_plus", C.c_double),
+                ("mean_minus", C.c_double)]
+
+
 class KernelProfile(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
 
@@ -111,6 +116,8 @@ def lib():
         L.epi_profile_admm.argtypes = [vp, vp, vp, vp, C.POINTER(ADMMOpts), C.POINTER(ADMMReport),
                                        C.POINTER(KernelProfile)]
         L.epi_profile_admm.restype = st
+        L.epi_corrected_images.argtypes = [vp, vp, vp, vp, C.POINTER(Quality)]
+        L.epi_corrected_images.restype = st
         L.epi_destroy.argtypes = [vp]
         L.epi_destroy.restype = None
         L.epi_gn_default_opts.argtypes = [C.POINTER(GNOpts)]
@@ -265,6 +272,18 @@ class Problem:
                     J=list(arrs["J"][:k + 1]), grad_norm=list(arrs["grad_norm"][:k + 1]),
                     pcg_relres=list(arrs["pcg_relres"][:k]), step=list(arrs["step"][:k]),
                     pcg_iters=list(its[:k]))
+
+    def corrected_images(self, b, out_plus=None, out_minus=None) -> dict:
+        """Corrected images at the field b into out_plus / out_minus (canonical cell
+        tensors, both or neither) and the quality measures {D, ncc, mean_plus, mean_minus}."""
+        q = Quality()
+        for t in (out_plus, out_minus):
+            if t is not None and tuple(t.shape) != self.shape_cells:
+                raise ValueError(f"expected cell tensors of shape {self.shape_cells}")
+        op = _ptr(out_plus) if out_plus is not None else None
+        om = _ptr(out_minus) if out_minus is not None else None
+        _check(lib().epi_corrected_images(self._h, self._faces(b), op, om, C.byref(q)))
+        return dict(D=q.D, ncc=q.ncc, mean_plus=q.mean_plus, mean_minus=q.mean_minus)
 
     def solve_admm(self, b, z, u, profile: bool = False, **kw) -> dict:
         """ADMM from the state (b, z, u), updated in place. With profile=True the solve runs

@@ -328,3 +328,38 @@ def test_admm_adaptive_rho_trajectory(shape, pe, alpha, rho0, mode, iters, prec)
         for k, (a, c, rk) in enumerate(zip(rep["r_dual"], ro.r_dual, ro.rho)):
             ok, msg = hist_ok([a], [c], scale * rk * P.v, prec)
             assert ok, ("r_dual", k, msg)
+
+
+# ---------------------------------------------------------------------------------------
+# Corrected images and quality
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,pe", SHAPES)
+def test_corrected_images(shape, pe):
+    import torch
+    v = generate(2, shape, pe)
+    P = O.make_problem(v.Ip, v.Im, v.h, 0.7)
+    with _problem(v, 0.7) as pr:
+        for bb in (np.zeros((P.L, P.M + 1)), v.b_true.reshape(P.L, -1), _smooth_field(P, 3, 0.6)):
+            outp = torch.zeros(pr.shape_cells, device=torch_dev())
+            outm = torch.zeros_like(outp)
+            q = pr.corrected_images(T(bb.reshape(pr.shape_faces)), outp, outm)
+            cp, cm = O.corrected_images(P, bb)
+            scale = max(np.abs(P.Ip).max(), np.abs(P.Im).max())
+            assert np.abs(N(outp).reshape(P.L, -1) - cp).max() <= 1e-5 * scale
+            assert np.abs(N(outm).reshape(P.L, -1) - cm).max() <= 1e-5 * scale
+            qo = O.image_quality(P, bb)
+            assert abs(q["D"] - qo["D"]) <= J_REL * qo["D"] + 1e-30
+            assert abs(q["ncc"] - qo["ncc"]) <= 1e-6
+            q2 = pr.corrected_images(T(bb.reshape(pr.shape_faces)))   # quality only
+            assert q2 == q
+
+
+def test_corrected_images_rejects_one_buffer():
+    import torch
+    from paper_1607_00531_amd import EpiError, EPI_EINVAL
+    v = generate(2, (24, 18), 1)
+    with _problem(v, 0.7) as pr:
+        outp = torch.zeros(pr.shape_cells, device=torch_dev())
+        with pytest.raises(EpiError) as e:
+            pr.corrected_images(T(np.zeros(pr.shape_faces)), outp, None)
+        assert e.value.status == EPI_EINVAL

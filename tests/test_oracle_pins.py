@@ -497,3 +497,54 @@ def test_adaptive_admm_equals_the_unscaled_iteration():
     np.testing.assert_allclose(zz, P.lines(z), rtol=0, atol=1e-12 * np.abs(zz).max())
     np.testing.assert_allclose(y / (rho * P.v), P.lines(u), rtol=0,
                                atol=1e-10 * np.abs(P.lines(u)).max())
+
+
+# ---------------------------------------------------------------------------------------
+# Corrected images and quality measures (Section 2 model relation; Section 3 discretisation)
+# ---------------------------------------------------------------------------------------
+def test_corrected_images_at_zero_and_integer_shifts():
+    from synth import generate
+    v = generate(3, (28, 20), 1)
+    P = O.make_problem(v.Ip, v.Im, v.h, 1.0)
+    cp, cm = O.corrected_images(P, np.zeros((P.L, P.M + 1)))
+    np.testing.assert_array_equal(cp, P.Ip)
+    np.testing.assert_array_equal(cm, P.Im)
+    for k in (1, 3, -2):
+        cp, cm = O.corrected_images(P, np.full((P.L, P.M + 1), k * P.hp))
+        ref_p, ref_m = np.zeros_like(P.Ip), np.zeros_like(P.Im)
+        for c in range(P.M):
+            if 0 <= c + k < P.M:
+                ref_p[:, c] = P.Ip[:, c + k]
+            if 0 <= c - k < P.M:
+                ref_m[:, c] = P.Im[:, c - k]
+        np.testing.assert_allclose(cp, ref_p, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(cm, ref_m, rtol=0, atol=1e-12)
+
+
+def test_corrected_images_converge_to_the_true_image():
+    """Noise-free pairs from a known field: at the true field both corrected images
+    approximate the undistorted image, with an error that falls under refinement (linear
+    interpolation of the measured samples: second order)."""
+    from synth import generate
+    errs = []
+    for m in (32, 64, 128):
+        v = generate(5, (m, m), 1, noise=0.0)
+        P = O.make_problem(v.Ip, v.Im, v.h, 1.0)
+        cp, cm = O.corrected_images(P, v.b_true.reshape(P.L, -1))
+        It = v.I_true.reshape(P.L, -1)
+        errs.append(max(np.abs(cp - It).max(), np.abs(cm - It).max()))
+    assert errs[0] > 2.5 * errs[1] > 2.5 * 2.5 * errs[2], errs
+
+
+def test_ncc_and_quality_consistency():
+    r = np.random.default_rng(0)
+    x = r.normal(size=500)
+    assert abs(O.ncc(x, x) - 1.0) < 1e-14
+    assert abs(O.ncc(x, 3.0 * x + 2.0) - 1.0) < 1e-14
+    assert abs(O.ncc(x, -x) + 1.0) < 1e-14
+    from synth import generate
+    v = generate(3, (16, 12, 6), 0)
+    P = O.make_problem(v.Ip, v.Im, v.h, 1.0)
+    b = v.b_true.reshape(P.L, -1)
+    q = O.image_quality(P, b)
+    assert abs(q["D"] - O.distance(P, b)) <= 1e-14 * O.distance(P, b)
