@@ -213,6 +213,42 @@ epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts* opts,
 epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
                           const epi_admm_opts* opts, epi_admm_report* rep);
 
+/* ---- Multilevel strategy (Section 4.4) ------------------------------------------------
+ * Grid transfer between a fine grid and a coarse grid whose cell counts are equal or half
+ * on every axis (m_fine[a] = m_coarse[a] or 2 m_coarse[a], canonical order PE first).
+ * Restriction of cell data (N floats): each coarse cell is the mean of its fine cells.
+ * Prolongation of a field on the PE faces (n floats): linear along PE (fine face 2i on the
+ * coarse face i, 2i + 1 at the midpoint), cell-centred weights 3/4 and 1/4 across (the
+ * farther neighbour clamped at the ends). Both are asynchronous on stream; EPI_EINVAL for
+ * sizes that are not such a pair. */
+epi_status epi_restrict_cells(const int32_t m_fine[3], const int32_t m_coarse[3],
+                              const float* d_fine, float* d_coarse, void* stream);
+epi_status epi_prolong_faces(const int32_t m_coarse[3], const int32_t m_fine[3],
+                             const float* d_coarse, float* d_fine, void* stream);
+
+#define EPI_ML_MAX_LEVELS 8
+
+/* Per-level outcome of epi_solve_multilevel_admm (index 0 = coarsest level). fallback[l] = 1
+ * if the restart average violated |D1 b| <= 1 and b0 = P b_c was used instead. */
+typedef struct {
+  int32_t levels;
+  int32_t m[EPI_ML_MAX_LEVELS][3];
+  int32_t iters[EPI_ML_MAX_LEVELS], converged[EPI_ML_MAX_LEVELS], fallback[EPI_ML_MAX_LEVELS];
+  double rho_last[EPI_ML_MAX_LEVELS];
+} epi_ml_report;
+
+/* Coarse-to-fine ADMM (Section 4.4) for the image pair of grid (the finest level): up to
+ * `levels` levels, every axis with an even count >= 4 halved per level (fewer levels when
+ * no axis can be halved), images restricted level by level, ADMM from b = z = u = 0 on the
+ * coarsest level with opts; between levels b0 = z0 = P((b_c + z_c) / 2) and u0 = 0 (the
+ * third restart strategy of Section 4.4), with b0 = P b_c if that average is infeasible;
+ * rho carries over between levels. The finest field is written to d_b (n floats,
+ * caller-owned). Allocates and frees the coarse levels' memory; synchronises stream. */
+epi_status epi_solve_multilevel_admm(const epi_grid* grid, const float* d_Iplus,
+                                     const float* d_Iminus, int32_t levels,
+                                     const epi_admm_opts* opts, void* stream, float* d_b,
+                                     epi_ml_report* rep);
+
 /* The same solve as epi_solve_admm (same kernels in the same order, same results),
  * launched one kernel at a time without the captured graph, with a pair of HIP events
  * around every kernel on the library's stream. prof receives the device time per kernel

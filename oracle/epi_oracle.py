@@ -44,6 +44,8 @@ __all__ = [
     "admm_residuals", "solve_admm", "ADMMReport", "augmented_lagrangian",
     "adapt_rho", "RHO_FIXED", "RHO_ADAPT", "RHO_ADAPT_FLOOR",
     "corrected_images", "ncc", "image_quality",
+    "coarse_count", "level_sizes", "restrict_cells", "prolong_faces", "feasible",
+    "solve_multilevel_admm",
     "dense_operators",
 ]
 
@@ -783,7 +785,117 @@ def solve_admm(P: Problem, b0=None, z0=None, u0=None, rho=1e3, max_iter=100,
 
 
 # ---------------------------------------------------------------------------------------
-# Dense operators from the Kronecker definitions (Section 3), for small grids only
+# Multilevel strategy (Section 4.4): coarse-to-fine levels, image restriction, field
+# prolongation and the ADMM restart of the third strategy. The paper defers the transfer
+# operators to the image-registration literature; the readings used here: every axis with
+# an even cell count of at least 4 is halved per level; images are restricted by averaging
+# the fine cells of a coarse cell; the field is prolongated linearly along PE on the faces
+# (even fine faces on coarse faces, odd ones at midpoints) and with the cell-centred
+# weights 3/4, 1/4 across (the nearer and the farther coarse neighbour, constant at the
+# ends). Along PE the prolongated field keeps the coarse D1 b values, across it is a convex
+# combination of coarse lines, so a feasible coarse field stays feasible.
+# ---------------------------------------------------------------------------------------
+def coarse_count(m: int) -> int:
+    return m // 2 if (m % 2 == 0 and m >= 4) else m
+
+
+def level_sizes(M: int, m2: int, m3: int, levels: int):
+    """Cell counts (M, m2, m3) of the levels, coarse to fine (fewer levels if no axis can
+    be halved any more)."""
+    sizes = [(M, m2, m3)]
+    while len(sizes) < levels:
+        a, b, c = sizes[-1]
+        nxt = (coarse_count(a), coarse_count(b), coarse_count(c) if c > 1 else 1)
+        if nxt == sizes[-1]:
+            break
+        sizes.append(nxt)
+    return sizes[::-1]
+
+
+def restrict_cells(x, fine, coarse):
+    """Cell array (m3, m2, M) on the fine grid -> coarse grid: mean of the fine cells of
+    each coarse cell (factor 1 or 2 per axis)."""
+    M, m2, m3 = fine
+    Mc, m2c, m3c = coarse
+    v = np.asarray(x, np.float64).reshape(m3, m2, M)
+    if Mc != M:
+        v = 0.5 * (v[:, :, 0::2] + v[:, :, 1::2])
+    if m2c != m2:
+        v = 0.5 * (v[:, 0::2, :] + v[:, 1::2, :])
+    if m3c != m3:
+        v = 0.5 * (v[0::2] + v[1::2])
+    return v
+
+
+def _prolong_cc(v, axis):
+    n = v.shape[axis]
+    lo = np.take(v, np.r_[0, np.arange(n - 1)], axis=axis)
+    hi = np.take(v, np.r_[np.arange(1, n), n - 1], axis=axis)
+    shape = list(v.shape)
+    shape[axis] = 2 * n
+    out = np.empty(shape)
+    ev = [slice(None)] * v.ndim
+    od = [slice(None)] * v.ndim
+    ev[axis] = slice(0, None, 2)
+    od[axis] = slice(1, None, 2)
+    out[tuple(ev)] = 0.75 * v + 0.25 * lo
+    out[tuple(od)] = 0.75 * v + 0.25 * hi
+    return out
+
+
+def prolong_faces(b, coarse, fine):
+    """Face array (m3c, m2c, Mc + 1) on the coarse grid -> fine grid (m3, m2, M + 1)."""
+    Mc, m2c, m3c = coarse
+    M, m2, m3 = fine
+    v = np.asarray(b, np.float64).reshape(m3c, m2c, Mc + 1)
+    if M != Mc:
+        f = np.empty((m3c, m2c, M + 1))
+        f[:, :, 0::2] = v
+        f[:, :, 1::2] = 0.5 * (v[:, :, :-1] + v[:, :, 1:])
+        v = f
+    if m2 != m2c:
+        v = _prolong_cc(v, 1)
+    if m3 != m3c:
+        v = _prolong_cc(v, 0)
+    return v
+
+
+def feasible(P: Problem, b, tol=1e-5) -> bool:
+    """|D1 b| <= 1 (+ tol) on every cell."""
+    return bool(np.all(np.abs(np.diff(P.lines(b), axis=1)) / P.hp <= 1.0 + tol))
+
+
+def solve_multilevel_admm(Ip, Im, h, alpha, levels=3, beta=10.0, gamma=1e-3, rho=1e3,
+                          **admm):
+    """Coarse-to-fine ADMM (Section 4.4) from b = z = u = 0 on the coarsest level. Between
+    levels: b0 = z0 = (P b + P z) / 2 (the third restart strategy; P = prolongation), taken
+    from (P b + P z) / 2 on the coarse data, u0 = 0; if that average violates |D1 b| <= 1
+    (z is not constrained) b0 = P b instead. rho carries over between levels (the rho of
+    the last iteration). Returns (b on the finest grid, per-level ADMM reports, sizes)."""
+    M, m2, m3 = Ip.shape[2], Ip.shape[1], Ip.shape[0]
+    sizes = level_sizes(M, m2, m3, levels)
+    imgs = {sizes[-1]: (np.asarray(Ip, np.float64), np.asarray(Im, np.float64))}
+    for lf, lc in zip(sizes[::-1][:-1], sizes[::-1][1:]):
+        fp, fm = imgs[lf]
+        imgs[lc] = (restrict_cells(fp, lf, lc), restrict_cells(fm, lf, lc))
+    reps = []
+    bc = zc = None
+    for li, sz in enumerate(sizes):
+        hl = tuple(h[a] * (M, m2, m3)[a] / sz[a] for a in range(3))
+        if m3 == 1:
+            hl = (hl[0], hl[1], h[2])
+        P = make_problem(imgs[sz][0], imgs[sz][1], hl, alpha, beta, gamma)
+        if bc is None:
+            b0 = z0 = np.zeros((sz[2], sz[1], sz[0] + 1))
+        else:
+            avg = prolong_faces(0.5 * (bc + zc), sizes[li - 1], sz)
+            z0 = avg
+            b0 = avg if feasible(P, avg) else prolong_faces(bc, sizes[li - 1], sz)
+        b, z, u, rep = solve_admm(P, b0, z0, np.zeros_like(b0), rho=rho, **admm)
+        reps.append(rep)
+        rho = rep.rho[-1] if rep.rho else rho
+        bc, zc = b, z
+    return bc, reps, sizes
 # ---------------------------------------------------------------------------------------
 def dense_operators(M: int, m2: int, m3: int, hp: float, h2: float, h3: float):
     """A1, D1, D2, D3 as dense matrices built from eq. A, eq. D1 and eq. d2d3, generalised

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libepi.so")
-SOURCES = ["epi_api.hip", "epi_line.hip", "epi_vec.hip", "epi_dct.hip", "epi_batch.hip"]
+SOURCES = ["epi_api.hip", "epi_line.hip", "epi_vec.hip", "epi_dct.hip", "epi_batch.hip",
+           "epi_multilevel.hip"]
 
 
 def hipcc() -> str:

@@ -316,6 +316,72 @@ class Problem:
         return out
 
 
+ML_MAX_LEVELS = 8
+
+
+class MLReport(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("m", (C.c_int32 * 3) * ML_MAX_LEVELS),
+                ("iters", C.c_int32 * ML_MAX_LEVELS), ("converged", C.c_int32 * ML_MAX_LEVELS),
+                ("fallback", C.c_int32 * ML_MAX_LEVELS), ("rho_last", C.c_double * ML_MAX_LEVELS)]
+
+
+def _ml_sigs(L):
+    if getattr(L, "_ml_sigs", False):
+        return L
+    vp, i3 = C.c_void_p, C.c_int32 * 3
+    L.epi_restrict_cells.argtypes = [i3, i3, vp, vp, vp]
+    L.epi_restrict_cells.restype = C.c_int
+    L.epi_prolong_faces.argtypes = [i3, i3, vp, vp, vp]
+    L.epi_prolong_faces.restype = C.c_int
+    L.epi_solve_multilevel_admm.argtypes = [C.POINTER(Grid), vp, vp, C.c_int32,
+                                            C.POINTER(ADMMOpts), vp, vp, C.POINTER(MLReport)]
+    L.epi_solve_multilevel_admm.restype = C.c_int
+    L._ml_sigs = True
+    return L
+
+
+def _counts(shape_cells):
+    m3, m2, M = (int(x) for x in shape_cells)
+    return (C.c_int32 * 3)(M, m2, m3)
+
+
+def restrict_cells(fine, coarse, stream=None):
+    """Coarse cell tensor = mean of the fine cells (canonical shapes (m3, m2, M), factors 1
+    or 2 per axis); asynchronous on the stream."""
+    L = _ml_sigs(lib())
+    _check(L.epi_restrict_cells(_counts(fine.shape), _counts(coarse.shape), _ptr(fine),
+                                _ptr(coarse), _stream_handle(stream)))
+
+
+def prolong_faces(coarse, fine, stream=None):
+    """Fine PE-face tensor from the coarse one (canonical shapes (m3, m2, M + 1))."""
+    L = _ml_sigs(lib())
+    mc = (coarse.shape[0], coarse.shape[1], coarse.shape[2] - 1)
+    mf = (fine.shape[0], fine.shape[1], fine.shape[2] - 1)
+    _check(L.epi_prolong_faces(_counts(mc), _counts(mf), _ptr(coarse), _ptr(fine),
+                               _stream_handle(stream)))
+
+
+def solve_multilevel_admm(Ip, Im, h, alpha, b, levels=3, beta=10.0, gamma=1e-3,
+                          precision="mixed", ndim=None, stream=None, **opts) -> dict:
+    """Coarse-to-fine ADMM (epi_solve_multilevel_admm); writes the finest field into b."""
+    L = _ml_sigs(lib())
+    g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, precision, ndim)
+    o = ADMMOpts()
+    L.epi_admm_default_opts(C.byref(o))
+    for k, v in opts.items():
+        setattr(o, k, RHO_MODES[v] if k == "rho_mode" and isinstance(v, str) else v)
+    if tuple(b.shape) != (Ip.shape[0], Ip.shape[1], Ip.shape[2] + 1):
+        raise ValueError("b must have the PE-face shape of the images")
+    rep = MLReport()
+    _check(L.epi_solve_multilevel_admm(C.byref(g), _ptr(Ip), _ptr(Im), int(levels), C.byref(o),
+                                       _stream_handle(stream), _ptr(b), C.byref(rep)))
+    n = rep.levels
+    return dict(levels=n, sizes=[tuple(rep.m[l]) for l in range(n)],
+                iters=list(rep.iters[:n]), converged=[bool(x) for x in rep.converged[:n]],
+                fallback=[bool(x) for x in rep.fallback[:n]], rho_last=list(rep.rho_last[:n]))
+
+
 EPI_EBUSY = 7
 STATUS_NAMES[EPI_EBUSY] = "EPI_EBUSY"
 

@@ -363,3 +363,60 @@ def test_corrected_images_rejects_one_buffer():
         with pytest.raises(EpiError) as e:
             pr.corrected_images(T(np.zeros(pr.shape_faces)), outp, None)
         assert e.value.status == EPI_EINVAL
+
+
+# ---------------------------------------------------------------------------------------
+# Multilevel strategy (Section 4.4)
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("fine,coarse", [((16, 12, 8), (8, 6, 4)), ((64, 64, 1), (32, 32, 1)),
+                                         ((240, 200, 110), (120, 100, 55)),
+                                         ((16, 9, 8), (8, 9, 4)), ((30, 26, 10), (15, 13, 5))])
+def test_restriction_and_prolongation(fine, coarse):
+    import torch
+    from paper_1607_00531_amd import restrict_cells, prolong_faces
+    r = np.random.default_rng(5)
+    M, m2, m3 = fine
+    Mc, m2c, m3c = coarse
+    x = r.normal(size=(m3, m2, M))
+    c = torch.zeros((m3c, m2c, Mc), device=torch_dev())
+    restrict_cells(T(x), c)
+    ref = O.restrict_cells(x, fine, coarse)
+    assert np.abs(N(c) - ref).max() <= 1e-6 * np.abs(ref).max()
+    bc = r.normal(size=(m3c, m2c, Mc + 1))
+    bf = torch.zeros((m3, m2, M + 1), device=torch_dev())
+    prolong_faces(T(bc), bf)
+    ref = O.prolong_faces(bc, coarse, fine)
+    assert np.abs(N(bf) - ref).max() <= 1e-6 * np.abs(ref).max()
+
+
+def test_transfer_rejects_sizes_that_are_not_a_pair():
+    import torch
+    from paper_1607_00531_amd import restrict_cells, EpiError, EPI_EINVAL
+    with pytest.raises(EpiError) as e:
+        restrict_cells(torch.zeros((4, 6, 8), device=torch_dev()),
+                       torch.zeros((2, 4, 4), device=torch_dev()))
+    assert e.value.status == EPI_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("shape,pe,alpha,rho0,mode,levels", [
+    ((64, 64), 1, 50.0, 1e6, "adapt_floor", 3),
+    ((32, 24, 16), 0, 5.0, 1e3, "fixed", 3)])
+def test_multilevel_admm(shape, pe, alpha, rho0, mode, levels, prec):
+    import torch
+    from paper_1607_00531_amd import solve_multilevel_admm
+    v = generate(0, shape, pe)
+    mid = {"fixed": O.RHO_FIXED, "adapt_floor": O.RHO_ADAPT_FLOOR}[mode]
+    opts = dict(max_iter=60, eps_abs=0.0, eps_rel=1e-3)
+    bo, reps, sizes = O.solve_multilevel_admm(v.Ip, v.Im, v.h, alpha, levels=levels, rho=rho0,
+                                              rho_mode=mid, **opts)
+    b = torch.zeros((v.m[2], v.m[1], v.m[0] + 1), device=torch_dev())
+    rep = solve_multilevel_admm(T(v.Ip), T(v.Im), v.h, alpha, b, levels=levels,
+                                precision=prec, rho=rho0, rho_mode=mode, **opts)
+    assert rep["sizes"] == sizes and rep["levels"] == len(sizes) == levels
+    for l, ro in enumerate(reps):
+        assert abs(rep["iters"][l] - ro.iters) <= 1, (l, rep["iters"], [r.iters for r in reps])
+        assert rep["converged"][l] == ro.converged
+    assert rep["rho_last"][-1] == reps[-1].rho[-1]
+    hp = v.h[0]
+    assert np.abs(N(b) - bo).max() / hp <= FIELD_VOX

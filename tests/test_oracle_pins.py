@@ -548,3 +548,67 @@ def test_ncc_and_quality_consistency():
     b = v.b_true.reshape(P.L, -1)
     q = O.image_quality(P, b)
     assert abs(q["D"] - O.distance(P, b)) <= 1e-14 * O.distance(P, b)
+
+
+# ---------------------------------------------------------------------------------------
+# Multilevel strategy (Section 4.4): level sizes, restriction, prolongation
+# ---------------------------------------------------------------------------------------
+def test_level_sizes_reproduce_the_papers_hierarchies():
+    """Section 5 (test data): three levels of 32x32, 64x64, 128x128 in 2D and of
+    50x50x33, 100x100x66, 200x200x132 in 3D."""
+    assert O.level_sizes(128, 128, 1, 3) == [(32, 32, 1), (64, 64, 1), (128, 128, 1)]
+    assert O.level_sizes(200, 200, 132, 3) == [(50, 50, 33), (100, 100, 66), (200, 200, 132)]
+    # an odd count stays while the others are still halved
+    assert O.level_sizes(240, 200, 110, 4) == [(30, 25, 55), (60, 50, 55), (120, 100, 55),
+                                               (240, 200, 110)]
+    assert O.level_sizes(7, 9, 5, 3) == [(7, 9, 5)]
+
+
+def test_restriction_keeps_constants_and_mass():
+    r = np.random.default_rng(3)
+    for fine, coarse in (((16, 12, 8), (8, 6, 4)), ((16, 12, 1), (8, 6, 1)), ((16, 9, 8), (8, 9, 4))):
+        M, m2, m3 = fine
+        x = r.normal(size=(m3, m2, M))
+        c = O.restrict_cells(x, fine, coarse)
+        vf = 1.0 / (M * m2 * m3)
+        vc = 1.0 / (coarse[0] * coarse[1] * coarse[2])
+        assert abs(c.sum() * vc - x.sum() * vf) <= 1e-12 * np.abs(x).sum() * vf
+        np.testing.assert_allclose(O.restrict_cells(np.full((m3, m2, M), 2.5), fine, coarse), 2.5)
+
+
+def test_prolongation_is_exact_on_linear_fields_and_keeps_feasibility():
+    r = np.random.default_rng(4)
+    coarse, fine = (8, 6, 4), (16, 12, 8)
+    Mc, m2c, m3c = coarse
+    M, m2, m3 = fine
+
+    def lin(Mx, my, mz, a, b_, c_):
+        xp = np.arange(Mx + 1) / Mx                       # PE faces
+        y = (np.arange(my) + 0.5) / my                    # cell centres across
+        z = (np.arange(mz) + 0.5) / mz
+        return a * xp[None, None, :] + b_ * y[None, :, None] + c_ * z[:, None, None]
+
+    bc = lin(Mc, m2c, m3c, 0.3, -0.7, 0.2)
+    bf = O.prolong_faces(bc, coarse, fine)
+    ref = lin(M, m2, m3, 0.3, -0.7, 0.2)
+    # exact away from the transverse ends (constant extrapolation there)
+    np.testing.assert_allclose(bf[1:-1, 1:-1], ref[1:-1, 1:-1], rtol=0, atol=1e-14)
+    # along PE the prolongated differences repeat the coarse ones; across it is convex
+    b = np.cumsum(r.normal(size=(m3c, m2c, Mc + 1)), axis=2)
+    b *= 0.9 / (np.abs(np.diff(b, axis=2)).max() * Mc)
+    d1c = np.abs(np.diff(b, axis=2)).max() * Mc
+    pf = O.prolong_faces(b, coarse, fine)
+    d1f = np.abs(np.diff(pf, axis=2)).max() * M
+    assert d1f <= d1c * (1 + 1e-12)
+
+
+def test_single_level_multilevel_is_plain_admm():
+    from synth import generate
+    v = generate(2, (20, 16), 1)
+    b1, reps, sizes = O.solve_multilevel_admm(v.Ip, v.Im, v.h, 1.0, levels=1, rho=1e3,
+                                              max_iter=12, eps_abs=0.0, eps_rel=0.0)
+    P = O.make_problem(v.Ip, v.Im, v.h, 1.0)
+    b2, _, _, rep = O.solve_admm(P, rho=1e3, max_iter=12, eps_abs=0.0, eps_rel=0.0)
+    assert sizes == [(P.M, P.m2, P.m3)]
+    np.testing.assert_array_equal(b1, b2)
+    assert reps[0].r_pri == rep.r_pri
