@@ -16,6 +16,8 @@ Readings of the paper adopted here (each one also listed in the design notes):
   * the gradient of the penalty is beta v D1^T phi'(D1 b) (D1^T: dimensions force it);
   * the QP gradient uses alpha v D1^T D1 b^k (gradient of (alpha v / 2)|D1 b|^2);
   * P_block = H_D + alpha v (D1^T D1 + M) + Hess(P) + gamma I with M = diag(D2^T D2 + D3^T D3);
+  * P_SGS splits H_JGN into strictly lower / diagonal / strictly upper parts in the face
+    order i + (M+1)(j + m2 k), the paper's x1-fastest order with x1 the PE axis;
   * gamma is used unscaled;
   * the step size of GN is chosen by Armijo backtracking (c1 = 1e-4, halving, at most
     ``ls_max`` trials) with an infeasible trial point counting as +inf;
@@ -39,6 +41,7 @@ __all__ = [
     "phi", "dphi", "d2phi",
     "objective", "gradient", "hessian_tridiag", "apply_laplacian_cross", "apply_D1tD1",
     "hessian_apply", "pblock_tridiag", "jacobi_diag", "thomas",
+    "hessian_sparse", "sgs_apply",
     "pcg", "gn_direction", "armijo", "solve_gnpcg", "GNReport",
     "dct_matrix", "dct_eigs", "zstep", "qp_active_set", "bstep_line", "bstep",
     "admm_residuals", "solve_admm", "ADMMReport", "augmented_lagrangian",
@@ -336,6 +339,50 @@ def jacobi_diag(P: Problem, tri) -> np.ndarray:
     return diag + P.alpha * P.v * _cross_diag(P)
 
 
+def hessian_sparse(P: Problem, tri):
+    """H_JGN as a sparse matrix over the faces in the order i + (M+1)(j + m2 k): the line
+    tridiagonal blocks ``tri`` plus alpha v (D2'D2 + D3'D3), D2 and D3 assembled from their
+    Kronecker definition (eq. d2d3) as sparse matrices."""
+    import scipy.sparse as sp
+    diag, off = tri
+    nf = P.M + 1
+    o = np.zeros((P.L, nf))
+    o[:, :-1] = off                         # o[l, i] couples faces i and i+1 of line l
+    ov = o.reshape(-1)[:-1]
+    H = sp.diags([diag.reshape(-1), ov, ov], [0, 1, -1], format="csr")
+
+    def dt(m, h):
+        if m < 2:
+            return sp.csr_matrix((0, m))
+        return sp.diags([-np.ones(m - 1) / h, np.ones(m - 1) / h], [0, 1], shape=(m - 1, m))
+
+    eye = lambda k: sp.identity(k, format="csr")  # noqa: E731
+    D2 = sp.kron(eye(P.m3), sp.kron(dt(P.m2, P.h2), eye(nf)))
+    D3 = sp.kron(dt(P.m3, P.h3), eye(P.m2 * nf))
+    return (H + P.alpha * P.v * (D2.T @ D2 + D3.T @ D3)).tocsr()
+
+
+def _sgs_parts(P: Problem, tri):
+    import scipy.sparse as sp
+    H = hessian_sparse(P, tri)
+    return sp.tril(H, 0, format="csr"), H.diagonal(), sp.triu(H, 0, format="csr")
+
+
+def _sgs_solve(P: Problem, parts, r) -> np.ndarray:
+    import scipy.sparse.linalg as sla
+    lower, dj, upper = parts                     # L + P_Jac, diag, U + P_Jac
+    y = sla.spsolve_triangular(lower, P.lines(r).reshape(-1), lower=True)
+    z = sla.spsolve_triangular(upper, dj * y, lower=False)
+    return z.reshape(P.L, P.M + 1)
+
+
+def sgs_apply(P: Problem, tri, r) -> np.ndarray:
+    """z = P_SGS^{-1} r with P_SGS = (L + P_Jac) P_Jac^{-1} (U + P_Jac) (eq. Psgs): L, U
+    the strictly lower and upper parts of H_JGN, P_Jac its diagonal; a forward triangular
+    solve, a diagonal scaling and a backward triangular solve."""
+    return _sgs_solve(P, _sgs_parts(P, tri), r)
+
+
 def thomas(diag: np.ndarray, off: np.ndarray, rhs: np.ndarray) -> np.ndarray:
     """Solve symmetric tridiagonal systems row-wise (Thomas algorithm, no pivoting).
     diag (L, N), off (L, N-1), rhs (L, N) or (L, N, K)."""
@@ -381,6 +428,9 @@ def pcg(P: Problem, tri, rhs, precond: str = "block", tol: float = 0.1, maxit: i
     elif precond == "jacobi":
         jd = jacobi_diag(P, tri)
         apply_M = lambda r: r / jd  # noqa: E731
+    elif precond == "sgs":
+        parts = _sgs_parts(P, tri)
+        apply_M = lambda r: _sgs_solve(P, parts, r)  # noqa: E731
     elif precond == "none":
         apply_M = lambda r: r.copy()  # noqa: E731
     else:

@@ -287,6 +287,78 @@ def test_pcg_converges_to_the_dense_gn_step_and_is_descent():
                                rtol=1e-9, atol=1e-12)
 
 
+def _textbook_sgs_sweep(A, rhs):
+    """One symmetric Gauss-Seidel iteration from x = 0 on a dense A: a forward sweep that
+    updates x_i in place from the newest values, then a backward sweep."""
+    n = len(rhs)
+    x = np.zeros(n)
+    for order in (range(n), range(n - 1, -1, -1)):
+        for i in order:
+            s = rhs[i]
+            for j in range(n):
+                if j != i:
+                    s -= A[i, j] * x[j]
+            x[i] = s / A[i, i]
+    return x
+
+
+@pytest.mark.parametrize("shape", [(6, 4, 3), (7, 5, 1), (5, 1, 4)])
+def test_sgs_is_one_forward_backward_gauss_seidel_sweep(shape):
+    """P_SGS^{-1} r (eq. Psgs) equals one textbook symmetric Gauss-Seidel iteration from
+    zero on H_JGN (the identity behind eq. Psgs in Saad's Ch. 4 and 10)."""
+    P = rand_problem(*shape, seed=31, alpha=0.6)
+    b = smooth_field(P, 32, 0.5)
+    tri = O.hessian_tridiag(P, b, True)
+    H = dense_from_apply(lambda x: O.hessian_apply(P, tri, x), P.n)
+    np.testing.assert_allclose(O.hessian_sparse(P, tri).toarray(), H, rtol=0, atol=1e-12 * np.abs(H).max())
+    r = np.random.default_rng(33).normal(size=(P.L, P.M + 1))
+    np.testing.assert_allclose(O.sgs_apply(P, tri, r).reshape(-1), _textbook_sgs_sweep(H, r.reshape(-1)),
+                               rtol=1e-10, atol=1e-12)
+
+
+def test_sgs_on_one_line_adds_the_diagonal_of_L_Dinv_U():
+    """A single PE line: H is tridiagonal with diagonal d and off-diagonal o, and
+    (L + D) D^-1 (U + D) = H + L D^-1 U is tridiagonal with o_{i-1}^2 / d_{i-1} added to
+    the diagonal at i >= 1; solved here with the banded LAPACK routine."""
+    P = rand_problem(23, 1, 1, seed=34, alpha=0.8)
+    b = smooth_field(P, 35, 0.6)
+    tri = O.hessian_tridiag(P, b, True)
+    d, o = tri[0][0], tri[1][0]
+    dd = d.copy()
+    dd[1:] += o ** 2 / d[:-1]
+    ab = np.zeros((3, P.M + 1))
+    ab[0, 1:], ab[1], ab[2, :-1] = o, dd, o
+    r = np.random.default_rng(36).normal(size=(1, P.M + 1))
+    np.testing.assert_allclose(O.sgs_apply(P, tri, r)[0], scipy.linalg.solve_banded((1, 1), ab, r[0]),
+                               rtol=1e-11, atol=1e-13)
+
+
+def test_sgs_of_a_diagonal_matrix_is_jacobi():
+    P = rand_problem(9, 1, 1, seed=37, alpha=0.0)
+    diag = np.random.default_rng(38).uniform(0.5, 2.0, size=(1, P.M + 1))
+    tri = (diag, np.zeros((1, P.M)))
+    r = np.random.default_rng(39).normal(size=(1, P.M + 1))
+    np.testing.assert_allclose(O.sgs_apply(P, tri, r), r / diag, rtol=1e-15)
+
+
+def test_sgs_inverse_is_spd_and_its_spectrum_lies_in_0_1():
+    """For SPD H, P_SGS = H + L D^-1 L' with D > 0, so P_SGS is SPD and the eigenvalues of
+    P_SGS^-1 H lie in (0, 1]; a transposed factor or D in place of D^-1 breaks one of these."""
+    P = rand_problem(7, 4, 3, seed=40, alpha=0.9)
+    b = smooth_field(P, 41, 0.5)
+    tri = O.hessian_tridiag(P, b, True)
+    H = dense_from_apply(lambda x: O.hessian_apply(P, tri, x), P.n)
+    Pinv = dense_from_apply(lambda x: O.sgs_apply(P, tri, x), P.n)
+    np.testing.assert_allclose(Pinv, Pinv.T, rtol=0, atol=1e-12 * np.abs(Pinv).max())
+    assert np.linalg.eigvalsh(0.5 * (Pinv + Pinv.T)).min() > 0
+    ev = np.linalg.eigvals(Pinv @ H).real
+    assert ev.min() > 0 and ev.max() <= 1 + 1e-10
+    g = O.gradient(P, b, True)
+    d, it, _ = O.pcg(P, tri, -g, "sgs", tol=1e-12, maxit=500)
+    np.testing.assert_allclose(d.reshape(-1), np.linalg.solve(H, -g.reshape(-1)), rtol=1e-8,
+                               atol=1e-10 * np.abs(d).max())
+
+
 def test_armijo_accepts_sufficient_decrease_and_rejects_infeasible():
     P = rand_problem(10, 4, 2, seed=16, alpha=0.4)
     b = smooth_field(P, 8, 0.3)
