@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define EPI_ABI_VERSION 2
+#define EPI_ABI_VERSION 3
 
 typedef enum {
   EPI_OK = 0,
@@ -62,8 +62,15 @@ typedef enum {
 typedef enum { EPI_PREC_FP32 = 0, EPI_PREC_MIXED = 1 } epi_precision;
 
 /* Preconditioner of the GN-PCG inner solve (Section 4.1): block-Jacobi (eq. Pblock; one
- * SPD tridiagonal system per PE line), Jacobi (diagonal of H_JGN), or none. */
-typedef enum { EPI_PRECOND_BLOCK = 0, EPI_PRECOND_JACOBI = 1, EPI_PRECOND_NONE = 2 } epi_precond;
+ * SPD tridiagonal system per PE line), Jacobi (diagonal of H_JGN), none, or symmetric
+ * Gauss-Seidel (eq. Psgs) in the face order i + (M+1)(j + m2 k). SGS is sequential by
+ * construction: its two sweeps take m2 + m3 - 1 dependent launches each. */
+typedef enum {
+  EPI_PRECOND_BLOCK = 0,
+  EPI_PRECOND_JACOBI = 1,
+  EPI_PRECOND_NONE = 2,
+  EPI_PRECOND_SGS = 3
+} epi_precond;
 
 /* Problem geometry and weights (Section 3). h = voxel edges (h[2] = 1 in 2D); the cell
  * volume v = h[0] h[1] h[2] plays the role of the paper's h^3. alpha weights the
@@ -197,6 +204,14 @@ epi_status epi_objective(epi_problem* p, const float* d_b, int32_t with_penalty,
  * the two non-PE axes in the arithmetic of grid->precision. d_w and d_z are n floats and
  * may alias. Does not synchronise. */
 epi_status epi_smooth_solve(epi_problem* p, const float* d_w, double rho, float* d_z);
+
+/* One application of a GN-PCG preconditioner (Section 4.1, eq. Pblock, eq. Psgs) built
+ * from H_JGN at the field d_b: d_z = P^{-1} d_r. d_b, d_r, d_z are n floats in canonical
+ * face layout, caller-owned; d_z must not alias d_r or d_b. precond is an epi_precond.
+ * EPI_EINVAL for an unknown precond or aliasing buffers; EPI_EINFEASIBLE if some
+ * |D1 b| >= 1 (the penalty Hessian is not defined there). Synchronises the stream. */
+epi_status epi_precond_apply(epi_problem* p, const float* d_b, int32_t precond,
+                             const float* d_r, float* d_z);
 
 /* Inexact Gauss-Newton-PCG on J_GN = D + alpha S + P (Section 4.1, eq. GNstep,
  * eq. inexactGNstep): d_b holds the starting guess on entry (must satisfy |D1 b| < 1) and

@@ -804,15 +804,42 @@ EPI_API epi_status epi_profile_admm(epi_problem* p, float* d_b, float* d_z, floa
 // ------------------------------------------------------------------------------------
 // GN-PCG (Section 4.1)
 // ------------------------------------------------------------------------------------
+EPI_API epi_status epi_precond_apply(epi_problem* p, const float* d_b, int32_t precond,
+                                     const float* d_r, float* d_z) {
+  if (!p || !d_b || !d_r || !d_z) return fail(EPI_EINVAL, "null argument");
+  if (precond < EPI_PRECOND_BLOCK || precond > EPI_PRECOND_SGS)
+    return fail(EPI_EINVAL, "unknown preconditioner %d", precond);
+  const auto overlap = [&](const float* x) { return x < d_z + p->n && d_z < x + p->n; };
+  if (overlap(d_r) || overlap(d_b)) return fail(EPI_EINVAL, "d_z must not overlap d_r or d_b");
+  enter(p);
+  epi_status s = eval_terms(p, d_b, 2, 1, p->g);
+  if (s != EPI_OK) return s;
+  HIPCHK(hipMemcpyAsync(p->st_h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+  HIPCHK(hipStreamSynchronize(p->exec));
+  if (p->st_h->eval_infeasible) {
+    leave(p);
+    return fail(EPI_EINFEASIBLE, "field has %d cells with |D1 b| >= 1", p->st_h->eval_infeasible);
+  }
+  if (precond == EPI_PRECOND_SGS)
+    launch_sgs(p->exec, p->P, p->la, p->hd, p->ho, d_r, d_z, p->st, 0);
+  else
+    launch_precond(p->exec, p->P, p->la, precond, p->hd, p->ho, d_r, d_z);
+  CHKLAUNCH();
+  HIPCHK(hipStreamSynchronize(p->exec));
+  leave(p);
+  return EPI_OK;
+}
+
 EPI_API epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts* opts,
                                       epi_gn_report* rep) {
   if (!p || !d_b || !opts) return fail(EPI_EINVAL, "null argument");
   if (opts->max_iter < 0 || opts->pcg_max < 0 || opts->ls_max < 1 || opts->precond < 0 ||
-      opts->precond > 2 || !(opts->eta > 0.0))
+      opts->precond > EPI_PRECOND_SGS || !(opts->eta > 0.0))
     return fail(EPI_EINVAL, "invalid GN options");
   enter(p);
   const long long n = p->n;
   const int lb = line_blocks(p->la);
+  const bool sgs = opts->precond == EPI_PRECOND_SGS;
   DevState* h = p->st_h;
   HIPCHK(hipStreamSynchronize(p->exec));
   memset(h, 0, sizeof(DevState));
@@ -858,9 +885,15 @@ EPI_API epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts
       break;
     }
     if (k >= opts->max_iter) break;
-    // PCG on H d = -g, the hessian blocks are in hd/ho from the last evaluation
-    launch_pcg_init(p->exec, p->P, p->la, opts->precond, p->g, p->hd, p->ho, p->x, p->r, p->zz,
-                    p->p, p->partial);
+    // PCG on H d = -g, the hessian blocks are in hd/ho from the last evaluation. With SGS
+    // the line kernels run unpreconditioned and the two sweeps then replace z (and p at the
+    // start) and the partial sums.
+    launch_pcg_init(p->exec, p->P, p->la, sgs ? EPI_PRECOND_NONE : opts->precond, p->g, p->hd,
+                    p->ho, p->x, p->r, p->zz, p->p, p->partial);
+    if (sgs) {
+      launch_sgs(p->exec, p->P, p->la, p->hd, p->ho, p->r, p->zz, p->st, 0);
+      launch_sgs_finish(p->exec, n, p->r, p->zz, p->p, p->partial, 1, p->st);
+    }
     CHKLAUNCH();
     FinArgs f{};
     f.partial = p->partial;
@@ -868,17 +901,21 @@ EPI_API epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts
     f.alpha = p->grid.alpha;
     f.beta = p->grid.beta;
     f.kind = FIN_PCG_INIT;
-    f.nb1 = lb;
+    f.nb1 = sgs ? flat_blocks(n) : lb;
     launch_finalize(p->exec, f, p->st);
     for (int it = 0; it < opts->pcg_max; ++it) {
       launch_matvec(p->exec, p->la, p->p, p->hd, p->ho, p->q, p->partial, p->st);
       f.kind = FIN_PCG_ALPHA;
       f.nb1 = flat_blocks(n);
       launch_finalize(p->exec, f, p->st);
-      launch_pcg_update(p->exec, p->P, p->la, opts->precond, p->hd, p->ho, p->x, p->r, p->zz,
-                        p->p, p->q, p->partial, p->st);
+      launch_pcg_update(p->exec, p->P, p->la, sgs ? EPI_PRECOND_NONE : opts->precond, p->hd,
+                        p->ho, p->x, p->r, p->zz, p->p, p->q, p->partial, p->st);
+      if (sgs) {
+        launch_sgs(p->exec, p->P, p->la, p->hd, p->ho, p->r, p->zz, p->st, 1);
+        launch_sgs_finish(p->exec, n, p->r, p->zz, nullptr, p->partial, 0, p->st);
+      }
       f.kind = FIN_PCG_UPDATE;
-      f.nb1 = lb;
+      f.nb1 = sgs ? flat_blocks(n) : lb;
       launch_finalize(p->exec, f, p->st);
       launch_pupdate(p->exec, n, p->zz, p->p, p->st);
       CHKLAUNCH();

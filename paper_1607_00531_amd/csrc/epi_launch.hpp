@@ -21,6 +21,12 @@ void launch_pcg_init(hipStream_t s, int P, LineArgs a, int precond, const float*
 void launch_pcg_update(hipStream_t s, int P, LineArgs a, int precond, const float* hdiag,
                        const float* hoff, float* x, float* r, float* z, const float* p,
                        const float* q, double* partial, const DevState* st);
+// z = Pinv r with a line-local preconditioner (BLOCK, JACOBI, NONE)
+void launch_precond(hipStream_t s, int P, LineArgs a, int precond, const float* hdiag,
+                    const float* hoff, const float* r, float* z);
+// symmetric Gauss-Seidel z = P_SGS^-1 r (all levels of both sweeps; z may not alias r)
+void launch_sgs(hipStream_t s, int P, LineArgs a, const float* hdiag, const float* hoff,
+                const float* r, float* z, const DevState* st, int gate);
 void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* z,
                        const float* u, float* w, int* hard_list, DevState* st, int hard_blocks,
                        const std::function<void(int)>& before,
@@ -34,6 +40,8 @@ void launch_matvec(hipStream_t s, LineArgs a, const float* p, const float* hdiag
                    const float* hoff, float* q, double* partial, const DevState* st);
 void launch_pupdate(hipStream_t s, long long n, const float* z, float* p, const DevState* st);
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial);
+void launch_sgs_finish(hipStream_t s, long long n, const float* r, const float* z, float* p,
+                       double* partial, int first, const DevState* st);
 void launch_gn_step(hipStream_t s, long long n, float* b, const float* d, double* partial,
                     const DevState* st);
 void launch_count_violations(hipStream_t s, LineArgs a, const float* b, float thr,

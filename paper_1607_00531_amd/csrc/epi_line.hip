@@ -271,6 +271,127 @@ __global__ __launch_bounds__(256) void k_pcg_update(LineArgs a, int precond,
   block_partials<NQ_PCG>(acc, partial, blockIdx.x);
 }
 
+// z = Pinv r for the line-local preconditioners (BLOCK, JACOBI, NONE) on their own.
+template <int P>
+__global__ __launch_bounds__(256) void k_precond(LineArgs a, int precond,
+                                                 const float* __restrict__ hdiag,
+                                                 const float* __restrict__ hoff,
+                                                 const float* __restrict__ r,
+                                                 float* __restrict__ z) {
+  __shared__ float sbuf[EPI_LINE_WAVES][3][LineBuf<P>::SIZE];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int line = blockIdx.x * EPI_LINE_WAVES + wave;
+  const bool valid = line < a.L;
+  const int lc = valid ? line : 0;
+  const int NF = a.M + 1;
+  const size_t base = (size_t)lc * NF;
+  const float* srcs[3] = {r + base, hdiag + base, hoff + base};
+  const int cnt[3] = {NF, NF, NF};
+  float v[3][P];
+  stage_in_n<P, 3>(srcs, cnt, valid, &sbuf[wave][0][0], v, lane);
+  precond_apply<P>(a, precond, v[1], v[2], cross_diag(a, lc % a.m2, lc / a.m2), v[0], lane);
+  stage_out<P>(z + base, NF, valid, &sbuf[wave][0][0], v[0], lane);
+}
+
+// ------------------------------------------------------------------------------------
+// Symmetric Gauss-Seidel preconditioner (eq. Psgs): z = (U + Dg)^-1 Dg (L + Dg)^-1 r with
+// H_JGN = L + Dg + U split in the face order i + (M+1)(j + m2 k). In that order the lower
+// neighbours of face (i, j, k) are (i-1, j, k), (i, j-1, k) and (i, j, k-1), so the lines
+// of one anti-diagonal j + k = s depend only on the lines of s - 1: each launch takes one
+// such level (one wavefront per line), the forward sweep from s = 0 up, the backward sweep
+// from the last level down. Along a line the triangular solve is the first-order
+// recurrence x_i = a_i x_{i-1} + b_i (x_{i+1} backward), evaluated by a wave-parallel
+// scan of affine maps: the same triangular solves as the sequential sweep, summed in a
+// different order.
+// ------------------------------------------------------------------------------------
+
+// Inclusive scan of the affine maps x -> A x + B over the blocked elements of a line,
+// lower indices applied first (BACK: higher indices first); returns x per element for a
+// zero value entering the line.
+template <int P, bool BACK>
+__device__ __forceinline__ void wave_affine_scan(const float (&av)[P], const float (&bv)[P],
+                                                 float (&x)[P], int lane) {
+  float A = 1.0f, B = 0.0f;
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    const int j = BACK ? P - 1 - t : t;
+    B = fmaf(av[j], B, bv[j]);
+    A *= av[j];
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const float An = BACK ? __shfl_down(A, d, 64) : __shfl_up(A, d, 64);
+    const float Bn = BACK ? __shfl_down(B, d, 64) : __shfl_up(B, d, 64);
+    const bool has = BACK ? lane + d < 64 : lane >= d;
+    if (has) {
+      B = fmaf(A, Bn, B);
+      A *= An;
+    }
+  }
+  float xin = BACK ? shfl_down0(B, 1, lane) : shfl_up0(B, 1, lane);
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    const int j = BACK ? P - 1 - t : t;
+    xin = fmaf(av[j], xin, bv[j]);
+    x[j] = xin;
+  }
+}
+
+// One level s of a sweep: lines (j, k) with j + k = s, k from kmin. Forward: z holds the
+// forward solution y of the lower levels and receives y on this level. Backward: z holds
+// y on this and the lower levels and z on the higher ones; this level's y becomes z.
+// gate: skip when the PCG has already stopped (not for the PCG start).
+template <int P, bool BACK>
+__global__ __launch_bounds__(256) void k_sgs_level(LineArgs a, int level, int kmin, int count,
+                                                   const float* __restrict__ hdiag,
+                                                   const float* __restrict__ hoff,
+                                                   const float* __restrict__ r, float* z,
+                                                   const DevState* st, int gate) {
+  if (gate && st->pcg_done) return;
+  __shared__ float sbuf[EPI_LINE_WAVES][5][LineBuf<P>::SIZE];
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int w = blockIdx.x * EPI_LINE_WAVES + wave;
+  const bool valid = w < count;
+  const int kk = kmin + (valid ? w : 0), jj = level - kk;
+  const int NF = a.M + 1;
+  const size_t base = (size_t)(jj + a.m2 * kk) * NF;
+  const size_t plane = (size_t)a.m2 * NF;
+  const float av = a.alpha * a.v;
+  // the two transverse neighbours on the already solved side (own line when absent)
+  const bool n2 = BACK ? jj < a.m2 - 1 : jj > 0;
+  const bool n3 = BACK ? kk < a.m3 - 1 : kk > 0;
+  const float c2 = n2 ? av * a.inv_h2sq : 0.0f, c3 = n3 ? av * a.inv_h3sq : 0.0f;
+  const float* own = BACK ? z + base : r + base;
+  const float* srcs[5] = {own, hdiag + base, hoff + base,
+                          n2 ? (BACK ? z + base + NF : z + base - NF) : own,
+                          n3 ? (BACK ? z + base + plane : z + base - plane) : own};
+  const int cnt[5] = {NF, NF, NF, NF, NF};
+  float v[5][P];
+  stage_in_n<P, 5>(srcs, cnt, valid, &sbuf[wave][0][0], v, lane);
+  const float dgx = av * cross_diag(a, jj, kk);
+  float oprev[P];
+  prev_cell<P>(v[2], oprev, lane);
+  float ca[P], cb[P], x[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int i = P * lane + j;
+    const float dg = v[1][j] + dgx;
+    const float idg = (i < NF) ? 1.0f / dg : 0.0f;
+    const float tr = fmaf(c2, v[3][j], c3 * v[4][j]);
+    if (BACK) {
+      // Dg_i z_i + o_i z_{i+1} = Dg_i y_i + c2 z(j+1) + c3 z(k+1)
+      ca[j] = (i < NF - 1) ? -v[2][j] * idg : 0.0f;
+      cb[j] = (i < NF) ? fmaf(tr, idg, v[0][j]) : 0.0f;
+    } else {
+      // Dg_i y_i + o_{i-1} y_{i-1} = r_i + c2 y(j-1) + c3 y(k-1)
+      ca[j] = (i >= 1) ? -oprev[j] * idg : 0.0f;
+      cb[j] = (v[0][j] + tr) * idg;
+    }
+  }
+  wave_affine_scan<P, BACK>(ca, cb, x, lane);
+  stage_out<P>(z + base, NF, valid, &sbuf[wave][0][0], x, lane);
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restrict__ bvec,
                                                     const float* __restrict__ zvec,
@@ -415,6 +536,33 @@ void launch_correct(hipStream_t s, int P, LineArgs a, const float* b, float* out
   const int nb = line_blocks(a);
   EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_correct<PP>), dim3(nb), dim3(256), 0, s, a, b, outp,
                                        outm, partial));
+}
+
+void launch_precond(hipStream_t s, int P, LineArgs a, int precond, const float* hdiag,
+                    const float* hoff, const float* r, float* z) {
+  const int nb = line_blocks(a);
+  EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_precond<PP>), dim3(nb), dim3(256), 0, s, a, precond,
+                                       hdiag, hoff, r, z));
+}
+
+void launch_sgs(hipStream_t s, int P, LineArgs a, const float* hdiag, const float* hoff,
+                const float* r, float* z, const DevState* st, int gate) {
+  const int levels = a.m2 + a.m3 - 1;
+  for (int t = 0; t < 2 * levels; ++t) {
+    const bool back = t >= levels;
+    const int lev = back ? 2 * levels - 1 - t : t;
+    const int kmin = lev - (a.m2 - 1) > 0 ? lev - (a.m2 - 1) : 0;
+    const int kmax = lev < a.m3 - 1 ? lev : a.m3 - 1;
+    const int count = kmax - kmin + 1;
+    const int nb = (count + EPI_LINE_WAVES - 1) / EPI_LINE_WAVES;
+    if (back) {
+      EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_sgs_level<PP, true>), dim3(nb), dim3(256), 0, s,
+                                           a, lev, kmin, count, hdiag, hoff, r, z, st, gate));
+    } else {
+      EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_sgs_level<PP, false>), dim3(nb), dim3(256), 0, s,
+                                           a, lev, kmin, count, hdiag, hoff, r, z, st, gate));
+    }
+  }
 }
 
 void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* z,

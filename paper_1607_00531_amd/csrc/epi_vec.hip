@@ -77,6 +77,27 @@ __global__ __launch_bounds__(256) void k_dot(long long n, const float* __restric
   block_partials<1>(acc, partial, blockIdx.x);
 }
 
+// After a symmetric Gauss-Seidel application: the PCG partial sums with the new z, in the
+// order of the line kernel they replace (first = 1: r.z, r.r as at the PCG start, and
+// p = z; first = 0: r.r, r.z as in the update). gate: skip once the PCG has stopped.
+__global__ __launch_bounds__(256) void k_sgs_finish(long long n, const float* __restrict__ r,
+                                                    const float* __restrict__ z,
+                                                    float* __restrict__ p, double* partial,
+                                                    int first, const DevState* st) {
+  if (!first && st->pcg_done) return;
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  double rz = 0.0, rr = 0.0;
+  for (long long f = lo + threadIdx.x; f < hi; f += blockDim.x) {
+    const float rv = r[f], zv = z[f];
+    rz += (double)rv * zv;
+    rr += (double)rv * rv;
+    if (first) p[f] = zv;
+  }
+  double acc[2] = {first ? rz : rr, first ? rr : rz};
+  block_partials<2>(acc, partial, blockIdx.x);
+}
+
 // b += lam d with the accepted step length (no-op when the line search failed);
 // partial sums |lam d|^2 and |b_old|^2 for the stopping tests (eq. stopping1).
 __global__ __launch_bounds__(256) void k_gn_step(long long n, float* __restrict__ b,
@@ -256,6 +277,11 @@ void launch_pupdate(hipStream_t s, long long n, const float* z, float* p, const 
 }
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial) {
   hipLaunchKernelGGL(k_dot, dim3(flat_blocks(n)), dim3(256), 0, s, n, x, y, partial);
+}
+void launch_sgs_finish(hipStream_t s, long long n, const float* r, const float* z, float* p,
+                       double* partial, int first, const DevState* st) {
+  hipLaunchKernelGGL(k_sgs_finish, dim3(flat_blocks(n)), dim3(256), 0, s, n, r, z, p, partial,
+                     first, st);
 }
 void launch_gn_step(hipStream_t s, long long n, float* b, const float* d, double* partial,
                     const DevState* st) {

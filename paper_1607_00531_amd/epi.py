@@ -18,7 +18,7 @@ EPI_OK, EPI_EINVAL, EPI_ENOMEM, EPI_EINFEASIBLE, EPI_ENUMERIC, EPI_EHIP, EPI_ENO
 STATUS_NAMES = {0: "EPI_OK", 1: "EPI_EINVAL", 2: "EPI_ENOMEM", 3: "EPI_EINFEASIBLE",
                 4: "EPI_ENUMERIC", 5: "EPI_EHIP", 6: "EPI_ENOTSUP"}
 PREC = {"fp32": 0, "mixed": 1}
-PRECOND = {"block": 0, "jacobi": 1, "none": 2}
+PRECOND = {"block": 0, "jacobi": 1, "none": 2, "sgs": 3}
 
 
 class EpiError(RuntimeError):
@@ -54,7 +54,7 @@ class GNReport(C.Structure):
 
 # penalty strategies of epi_admm_opts.rho_mode
 RHO_MODES = {"fixed": 0, "adapt": 1, "adapt_floor": 2}
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 
 class ADMMOpts(C.Structure):
@@ -118,6 +118,8 @@ def lib():
         L.epi_profile_admm.restype = st
         L.epi_corrected_images.argtypes = [vp, vp, vp, vp, C.POINTER(Quality)]
         L.epi_corrected_images.restype = st
+        L.epi_precond_apply.argtypes = [vp, vp, C.c_int32, vp, vp]
+        L.epi_precond_apply.restype = st
         L.epi_destroy.argtypes = [vp]
         L.epi_destroy.restype = None
         L.epi_gn_default_opts.argtypes = [C.POINTER(GNOpts)]
@@ -250,6 +252,15 @@ class Problem:
         import torch
         z = torch.empty_like(w) if out is None else out
         _check(lib().epi_smooth_solve(self._h, self._faces(w), float(rho), self._faces(z)))
+        return z
+
+    def precond_apply(self, b, r, precond="block", out=None):
+        """z = P^-1 r with the GN-PCG preconditioner built from H_JGN(b) (block, jacobi,
+        none or sgs); out must not overlap r or b."""
+        import torch
+        z = torch.empty_like(r) if out is None else out
+        pc = PRECOND[precond] if isinstance(precond, str) else int(precond)
+        _check(lib().epi_precond_apply(self._h, self._faces(b), pc, self._faces(r), self._faces(z)))
         return z
 
     def solve_gnpcg(self, b, **kw) -> dict:

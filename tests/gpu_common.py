@@ -38,3 +38,27 @@ def hist_ok(gpu, cpu, scale, prec):
         i = bad[0]
         return False, f"iteration {i}: gpu {gpu[i]:.6e} cpu {cpu[i]:.6e} limit {lim[i]:.2e}"
     return True, ""
+
+
+def oracle_precond(P, tri, r, precond):
+    """z = P^-1 r by the oracle for the four GN-PCG preconditioners."""
+    import oracle as O
+    if precond == "block":
+        return O.thomas(*O.pblock_tridiag(P, tri), r)
+    if precond == "jacobi":
+        return r / O.jacobi_diag(P, tri)
+    if precond == "sgs":
+        return O.sgs_apply(P, tri, r)
+    return r.copy()
+
+
+def precond_tol(P, tri, r, precond, zo, seed=1):
+    """Bar for z = P^-1 r against the oracle, relative to max|z|: 16 times the change of z
+    under a random relative perturbation of 2^-24 (one float32 rounding) of every entry of
+    the Hessian blocks, plus 1e-6. The GPU assembles those entries in float32, so its z can
+    differ by a few such roundings amplified by the conditioning of P (up to ~5e5 for the
+    block-Jacobi lines of 500 faces)."""
+    rng = np.random.default_rng(seed)
+    trp = tuple(t * (1.0 + 2.0 ** -24 * rng.uniform(-1.0, 1.0, size=t.shape)) for t in tri)
+    sens = np.abs(oracle_precond(P, trp, r, precond) - zo).max() / np.abs(zo).max()
+    return 16.0 * sens + 1e-6
