@@ -227,6 +227,37 @@ static std::vector<float> pack_f32(const std::vector<double>& A, int m, int& RT,
   return out;
 }
 
+// Even/odd split of the DCT for the split-bfloat16 kernels (c = ceil(m/2), f = floor(m/2)):
+// the even half holds rows k = 2r (forward: C[2r][q], q < c; inverse: C[2q][n], n, q < c),
+// the odd half rows k = 2r + 1 (forward: C[2r+1][q]; inverse: C[2q+1][n]; n, r, q < f), in
+// row tiles [0, RTh) and [RTh, 2 RTh) with KS steps of 32 over the half's own contraction.
+static std::vector<uint16_t> pack_bf16_split(const std::vector<double>& C, int m, bool inverse,
+                                             int& RT, int& KS) {
+  const int ce = (m + 1) / 2, fo = m / 2;
+  const int RTh = (ce + 15) / 16;
+  RT = 2 * RTh;
+  KS = (ce + 31) / 32;
+  const size_t nfr = (size_t)RT * KS * 64 * 8;
+  std::vector<uint16_t> out(2 * nfr, 0);
+  for (int rt = 0; rt < RT; ++rt)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e) {
+          const int half = rt / RTh, row = 16 * (rt % RTh) + (l & 15);
+          const int q = 32 * ks + 8 * (l >> 4) + e;
+          const int cnt = half ? fo : ce;
+          double val = 0.0;
+          if (row < cnt && q < cnt)
+            val = inverse ? C[(size_t)(2 * q + half) * m + row] : C[(size_t)(2 * row + half) * m + q];
+          const uint16_t hi = bf16_rn((float)val);
+          const uint16_t lo = bf16_rn((float)(val - (double)bf16_to_f(hi)));
+          const size_t idx = (((size_t)rt * KS + ks) * 64 + l) * 8 + e;
+          out[idx] = hi;
+          out[nfr + idx] = lo;
+        }
+  return out;
+}
+
 static epi_status upload_matrix(int precision, const std::vector<double>& A, int m, void** dst,
                                 int& RT, int& KS) {
   if (precision == EPI_PREC_MIXED) {
@@ -253,15 +284,29 @@ epi_status epi::build_dct_tables(int m2, int m3, double h2, double h3, int preci
     for (int a = 0; a < m; ++a)
       for (int j = 0; j < m; ++j) Ct[(size_t)j * m + a] = C[(size_t)a * m + j];
     epi_status s;
-    if (axis == 2) {
-      if ((s = upload_matrix(precision, C, m, &t->A2f, RT, KS)) != EPI_OK) return s;
-      if ((s = upload_matrix(precision, Ct, m, &t->A2i, t->RT2, t->KS2)) != EPI_OK) return s;
+    void** fw = axis == 2 ? &t->A2f : &t->A3f;
+    void** iv = axis == 2 ? &t->A2i : &t->A3i;
+    int& RTa = axis == 2 ? t->RT2 : t->RT3;
+    int& KSa = axis == 2 ? t->KS2 : t->KS3;
+    if (precision == EPI_PREC_MIXED) {
+      // even/odd split; spectral data in half order (even k first, then odd k)
+      for (int inv = 0; inv < 2; ++inv) {
+        auto v = pack_bf16_split(C, m, inv == 1, RTa, KSa);
+        void** dst = inv ? iv : fw;
+        HIPCHK(hipMalloc(dst, v.size() * sizeof(uint16_t)));
+        HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+      }
     } else {
-      if ((s = upload_matrix(precision, C, m, &t->A3f, RT, KS)) != EPI_OK) return s;
-      if ((s = upload_matrix(precision, Ct, m, &t->A3i, t->RT3, t->KS3)) != EPI_OK) return s;
+      if ((s = upload_matrix(precision, C, m, fw, RT, KS)) != EPI_OK) return s;
+      if ((s = upload_matrix(precision, Ct, m, iv, RTa, KSa)) != EPI_OK) return s;
     }
     std::vector<float> lam(m);
-    for (int j = 0; j < m; ++j) lam[j] = (float)((2.0 - 2.0 * cos(M_PI * j / m)) / (h * h));
+    const int ce = (m + 1) / 2;
+    for (int j = 0; j < m; ++j) {
+      // eigenvalue of spectral row j (natural order, or half order with the split)
+      const int k = (precision == EPI_PREC_MIXED) ? (j < ce ? 2 * j : 2 * (j - ce) + 1) : j;
+      lam[j] = (float)((2.0 - 2.0 * cos(M_PI * k / m)) / (h * h));
+    }
     float** dl = axis == 2 ? &t->lam2 : &t->lam3;
     HIPCHK(hipMalloc(dl, m * sizeof(float)));
     HIPCHK(hipMemcpy(*dl, lam.data(), m * sizeof(float), hipMemcpyHostToDevice));
@@ -513,6 +558,7 @@ GemmArgs epi::make_gemm_axis3(int M, int m2, int m3, float alpha, const DctTable
   g.col_tiles = (g.ncol + 63) / 64;
   g.RT = t.RT3;
   g.KS = t.KS3;
+  g.dir = inverse ? 1 : 0;
   g.A1 = inverse ? t.A3i : t.A3f;
   g.A2 = nullptr;
   g.alpha = alpha;

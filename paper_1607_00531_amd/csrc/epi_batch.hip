@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void k_batch_finalize(BatchDev* bd) {
 // ------------------------------------------------------------------------------------
 static size_t dct_class_lds(int prec, bool small) {
   GemmArgs g{};
-  g.KS = small ? (prec == 1 ? 4 : 32) : (prec == 1 ? 8 : 64);
+  g.KS = small ? (prec == 1 ? 2 : 32) : (prec == 1 ? 4 : 64);   // bf16: steps of one half
   g.RT = small ? 8 : 16;
   return dct_lds_bytes(prec, g);
 }

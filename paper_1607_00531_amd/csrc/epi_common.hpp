@@ -68,6 +68,7 @@ struct GemmArgs {
   int nbatch;
   int col_tiles;
   int RT, KS;        // 16-row tiles and contraction steps of the packed matrices
+  int dir;           // unfused split-bfloat16 pass: 0 forward, 1 inverse
   const void* A1;    // packed forward matrix fragments
   const void* A2;    // packed inverse matrix fragments (fused pass only)
   const float* lam_row;    // eigenvalues along the transformed axis (fused pass)

@@ -71,13 +71,30 @@ __device__ __forceinline__ void acc_to_lds(float* T, const f4 (&acc)[SLOTS][4], 
   }
 }
 
+// Output row -> value of the LDS tile [row][col]. OUT_PLAIN: the row itself. With the
+// even/odd split (N = transform length, c = ceil(N/2), f = floor(N/2), odd block from tile
+// row hrow): OUT_HALF_ORDER: spectral output in half order (rows < c even block, then the
+// odd block); OUT_EVEN_ODD: spatial output x_n = E_n + O_n, x_{N-1-n} = E_n - O_n.
+enum { OUT_PLAIN = 0, OUT_HALF_ORDER = 1, OUT_EVEN_ODD = 2 };
+template <int OUT>
+__device__ __forceinline__ float tile_value(const float* T, int row, int col, int N, int hrow) {
+  constexpr int LD = DCT_NT + 4;
+  if (OUT == OUT_PLAIN) return T[row * LD + col];
+  const int ce = (N + 1) / 2, fo = N / 2;
+  if (OUT == OUT_HALF_ORDER) return T[(row < ce ? row : hrow + row - ce) * LD + col];
+  const int n = row < ce ? row : N - 1 - row;
+  const float e = T[n * LD + col];
+  const float o = (n < fo) ? T[(hrow + n) * LD + col] : 0.0f;
+  return row < ce ? e + o : e - o;
+}
+
 // Epilogue of the last pass from the LDS tile, one row of 64 consecutive columns per
 // wavefront (coalesced; the row is uniform over the wavefront). EPI 0: store. EPI 1: ADMM
 // u-step and residual sums: z_new = value, u_new = u + b - z_new (eq. admmStep3); sums
 // |b - z|^2, |z - z_old|^2, |z|^2, |u|^2, |b|^2 into the partial buffer.
-template <int EPI, int NW>
+template <int EPI, int NW, int OUT>
 __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const float* T, size_t bofs,
-                                              int c0, int pslot) {
+                                              int c0, int pslot, int hrow) {
   double acc[NQ_ADMM_E] = {0, 0, 0, 0, 0};
   const int col = threadIdx.x & (DCT_NT - 1);
   const unsigned col4 = (unsigned)col * 4u;
@@ -87,7 +104,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const float* T,
   if (EPI == 0) {
     float* ob = g.out + bofs + c0;
     for (int row = r0; row < g.rows; row += RS)
-      if (cok) st_at<float>(ob + (size_t)row * g.ld, col4, T[row * (DCT_NT + 4) + col]);
+      if (cok) st_at<float>(ob + (size_t)row * g.ld, col4, tile_value<OUT>(T, row, col, g.rows, hrow));
   } else {
     // U rows per thread in flight: all their loads are issued before the first store
     // (the stores to z and u could alias the loads as far as the compiler knows)
@@ -112,7 +129,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const float* T,
         const int row = rb + RS * q;
         if (cok && row < g.rows) {
           const size_t ro = (size_t)row * g.ld;
-          const float val = T[row * (DCT_NT + 4) + col];
+          const float val = tile_value<OUT>(T, row, col, g.rows, hrow);
           const float r = bb[q] - val;
           const float un = uo[q] + r;
           st_at<float>(zb0 + ro, col4, val);
@@ -131,20 +148,32 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const float* T,
 }
 
 // ------------------------------------------------------------------------------------
-// split-bfloat16 variant. KSM: maximum contraction steps of 32 (rows <= 32 KSM); NW
-// wavefronts per workgroup; SLOTS = 2 KSM / NW row tiles of 16 per wavefront.
+// split-bfloat16 variant with the even/odd decomposition of the DCT. With c = ceil(N/2),
+// f = floor(N/2) and C[k][N-1-n] = (-1)^k C[k][n]:
+//   forward  y_2r   = sum_{q<c} C[2r][q]   s_q,  s_q = x_q + x_{N-1-q} (s_mid = x_mid, N odd)
+//            y_2r+1 = sum_{q<f} C[2r+1][q] d_q,  d_q = x_q - x_{N-1-q}
+//   inverse  E_n = sum_{r<c} C[2r][n] y_2r,  O_n = sum_{r<f} C[2r+1][n] y_2r+1,
+//            x_n = E_n + O_n, x_{N-1-n} = E_n - O_n (x_mid = E_mid, N odd)
+// Two half-size products replace one N x N product. Spectral data between the passes is
+// kept in half order: even k first (row r <-> k = 2r), then odd k (row c + r <-> 2r + 1).
+// The packed matrices hold the even half in row tiles [0, RTh) and the odd half in
+// [RTh, 2 RTh), each with KS steps of 32 over its own contraction block; in LDS the even
+// block sits at contraction offset 0 and the odd block at KS * 32.
+// KSF: maximum steps of 32 of the whole length (N <= 32 KSF), KSM = KSF / 2 those of a
+// half; NW wavefronts per workgroup, the first NW / 2 on the even half, the others on the
+// odd half, each with up to SLOTS = 4 KSM / NW row tiles.
 // ------------------------------------------------------------------------------------
-// acc[s][ct] += A(row tile wave + NW s) * B(LDS tile, column tile ct) over all contraction
-// steps. The A fragments stream from L2 PD steps ahead of the products that use them; the
-// step loop is unrolled over its compile-time bound KSM so that the fragment ring stays in
-// registers.
-template <int SLOTS, int KSM, int PD, int NW>
+// acc[s][ct] += A(row tile rt0 + rstep s) * B(LDS tile from contraction offset koff, column
+// tile ct) over all contraction steps. The A fragments stream from L2 PD steps ahead of the
+// products that use them; the step loop is unrolled over its compile-time bound KSM so that
+// the fragment ring stays in registers.
+template <int SLOTS, int KSM, int PD>
 __device__ __forceinline__ void gemm_bf16(const us8* __restrict__ A, size_t frag_stride, int KS,
-                                          int wave, int lane, int nslot,
+                                          int rt0, int rstep, int lane, int nslot,
                                           const unsigned short* Lhi, const unsigned short* Llo,
-                                          int KP, f4 (&acc)[SLOTS][4]) {
+                                          int KP, int koff, f4 (&acc)[SLOTS][4]) {
   // fragment (row tile rt, step ks) of lane l sits at ((rt * KS + ks) * 64 + l) * 16 bytes;
-  // rt = wave + NW s is uniform, so only lane * 16 is a per-lane offset
+  // rt = rt0 + rstep s is uniform, so only lane * 16 is a per-lane offset
   const us8* Alo = A + frag_stride;
   const unsigned lane16 = (unsigned)lane * 16u;
   us8 fh[KSM][SLOTS], fl[KSM][SLOTS];
@@ -154,7 +183,7 @@ __device__ __forceinline__ void gemm_bf16(const us8* __restrict__ A, size_t frag
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
         if (s < nslot) {
-          const size_t fu = ((size_t)(wave + NW * s) * KS + ks) * 64;
+          const size_t fu = ((size_t)(rt0 + rstep * s) * KS + ks) * 64;
           fh[ks][s] = ld_at<us8>(A + fu, lane16);
           fl[ks][s] = ld_at<us8>(Alo + fu, lane16);
         }
@@ -168,7 +197,7 @@ __device__ __forceinline__ void gemm_bf16(const us8* __restrict__ A, size_t frag
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           if (s < nslot) {
-            const size_t fu = ((size_t)(wave + NW * s) * KS + ks + PD) * 64;
+            const size_t fu = ((size_t)(rt0 + rstep * s) * KS + ks + PD) * 64;
             fh[(ks + PD) % KSM][s] = ld_at<us8>(A + fu, lane16);
             fl[(ks + PD) % KSM][s] = ld_at<us8>(Alo + fu, lane16);
           }
@@ -178,7 +207,7 @@ __device__ __forceinline__ void gemm_bf16(const us8* __restrict__ A, size_t frag
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) {
         const int col = ct * 16 + (lane & 15);
-        const int k0 = ks * 32 + (lane >> 4) * 8;
+        const int k0 = koff + ks * 32 + (lane >> 4) * 8;
         bh[ct] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Lhi[col * KP + k0]));
         bl[ct] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const us8*>(&Llo[col * KP + k0]));
       }
@@ -208,18 +237,42 @@ __device__ __forceinline__ void gemm_bf16(const us8* __restrict__ A, size_t frag
 #endif
 template <int KSM>
 struct GemmPD {
-  static constexpr int value = KSM <= 4 ? EPI_GEMM_PD_SMALL : EPI_GEMM_PD_BIG;
+  static constexpr int value = KSM <= 2 ? EPI_GEMM_PD_SMALL : EPI_GEMM_PD_BIG;
 };
+
+// Writes the accumulators (row tiles rt0 + rstep s) to the float32 LDS tile [row][col].
+template <int SLOTS>
+__device__ __forceinline__ void acc_rows_to_lds(float* T, const f4 (&acc)[SLOTS][4], int rt0,
+                                                int rstep, int lane, int nslot) {
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s) {
+    if (s < nslot) {
+      const int r0 = (rt0 + rstep * s) * 16 + (lane >> 4) * 4;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) T[(r0 + r) * (DCT_NT + 4) + ct * 16 + (lane & 15)] = acc[s][ct][r];
+    }
+  }
+}
 
 // One 64-column tile of one batch entry: fill, product(s), epilogue. pslot = index of this
 // tile's partial sums (EPI 1). Every thread of the workgroup (NW wavefronts) must call it.
-// Rows up to 32 KSM; row tile rt belongs to wave rt % NW.
-template <bool FUSED, int EPI, int KSM, int NW>
+// FUSED: spatial in, forward, spectral scale, inverse, spatial out; otherwise g.dir = 0
+// (spatial in, spectral out in half order) or 1 (spectral in half order, spatial out).
+template <bool FUSED, int EPI, int KSF, int NW>
 __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int c0, int pslot,
                                               unsigned short* lds_bf) {
-  constexpr int SLOTS = 2 * KSM / NW;
-  constexpr int NIT = (4 * KSM + NW - 1) / NW;   // 8-row groups per thread in the fill
-  const int KP = g.KS * 32 + 8;
+  constexpr int KSM = KSF / 2;                     // KSF: steps of 32 of the whole length
+  constexpr int HW = NW / 2;                       // wavefronts per half
+  constexpr int SLOTS = (2 * KSM + HW - 1) / HW;   // row tiles per wavefront (RTh <= 2 KSM)
+  constexpr int NG = 4 * KSM;                      // 8-row groups per half (maximum)
+  constexpr int NIT = (NG + NW - 1) / NW;
+  const int N = g.rows, ce = (N + 1) / 2, fo = N / 2;
+  const int KPh = g.KS * 32;                       // contraction extent of one half
+  const int KP = 2 * KPh + 8;
+  const int RTh = g.RT / 2;
+  const bool fwd_in = FUSED || g.dir == 0;
   unsigned short* Lhi = lds_bf;
   unsigned short* Llo = lds_bf + DCT_NT * KP;
   const size_t bofs = (size_t)batch * g.bstride;
@@ -227,22 +280,27 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
-  // fill: thread handles (column = lane, group kg = wave + NW it of 8 consecutive rows) for
-  // the 4 KS groups; the rows are uniform over the wavefront; all global loads are issued
-  // before the first conversion
+  // fill: thread handles (column = lane, group kg = wave + NW it of 8 contraction positions
+  // q of both halves); the positions are uniform over the wavefront; all global loads are
+  // issued before the first conversion
   {
     const unsigned lane4 = (unsigned)lane * 4u;
     const bool cok = c0 + lane < g.ncol;
     const int ngroups = 4 * g.KS;
-    float v[NIT][8];
+    float va[NIT][8], vb[NIT][8];
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int kg = wave + NW * it;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int k = kg * 8 + e;
-        v[it][e] = (kg < ngroups && k < g.rows && cok) ? ld_at<float>(in + (size_t)k * g.ld, lane4)
-                                                       : 0.0f;
+        const int q = kg * 8 + e;
+        const bool live = kg < ngroups && cok;
+        // forward: x_q and x_{N-1-q}; inverse: spectral rows q (even) and c + q (odd)
+        const int ra = q, rb = fwd_in ? N - 1 - q : ce + q;
+        const bool oka = live && q < ce;
+        const bool okb = live && q < fo;
+        va[it][e] = oka ? ld_at<float>(in + (size_t)ra * g.ld, lane4) : 0.0f;
+        vb[it][e] = okb ? ld_at<float>(in + (size_t)(okb ? rb : 0) * g.ld, lane4) : 0.0f;
       }
     }
 #pragma unroll
@@ -250,46 +308,65 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
       const int kg = wave + NW * it;
       if (kg < ngroups) {
         const int col = lane;
-        u4v hv, lv;
+        u4v hv0, lv0, hv1, lv1;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
+          float ev[2], od[2];
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const float a = va[it][2 * e + t], b = vb[it][2 * e + t];
+            // forward: the pair sum / difference (b = 0 for q >= f, so s_mid = x_mid)
+            ev[t] = fwd_in ? a + b : a;
+            od[t] = fwd_in ? a - b : b;
+            if (fwd_in && kg * 8 + 2 * e + t >= fo) od[t] = 0.0f;
+          }
           unsigned h, l;
-          split_bf2(v[it][2 * e], v[it][2 * e + 1], h, l);
-          hv[e] = h;
-          lv[e] = l;
+          split_bf2(ev[0], ev[1], h, l);
+          hv0[e] = h;
+          lv0[e] = l;
+          split_bf2(od[0], od[1], h, l);
+          hv1[e] = h;
+          lv1[e] = l;
         }
-        *reinterpret_cast<u4v*>(&Lhi[col * KP + kg * 8]) = hv;
-        *reinterpret_cast<u4v*>(&Llo[col * KP + kg * 8]) = lv;
+        *reinterpret_cast<u4v*>(&Lhi[col * KP + kg * 8]) = hv0;
+        *reinterpret_cast<u4v*>(&Llo[col * KP + kg * 8]) = lv0;
+        *reinterpret_cast<u4v*>(&Lhi[col * KP + KPh + kg * 8]) = hv1;
+        *reinterpret_cast<u4v*>(&Llo[col * KP + KPh + kg * 8]) = lv1;
       }
     }
   }
   __syncthreads();
 
-  const int nslot = (g.RT - wave + NW - 1) / NW;   // row tiles rt = wave + NW s
+  const int half = wave / HW, lw = wave % HW;
+  const int rt0 = half * RTh + lw;                 // row tiles rt0 + HW s of this half
+  const int nslot = (RTh - lw + HW - 1) / HW;
+  const int koff = half * KPh;
   f4 acc[SLOTS][4];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[s][ct] = f4{0.f, 0.f, 0.f, 0.f};
   const size_t frag_stride = (size_t)g.RT * g.KS * 64;   // hi block, then lo block
-  gemm_bf16<SLOTS, KSM, GemmPD<KSM>::value, NW>(reinterpret_cast<const us8*>(g.A1), frag_stride,
-                                                g.KS, wave, lane, nslot, Lhi, Llo, KP, acc);
+  gemm_bf16<SLOTS, KSM, GemmPD<KSM>::value>(reinterpret_cast<const us8*>(g.A1), frag_stride, g.KS,
+                                            rt0, HW, lane, nslot, Lhi, Llo, KP, koff, acc);
 
   if (FUSED) {
-    // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)), then the inverse
+    // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)) in half order, then
+    // the inverse from the same LDS blocks
     const float rho = (float)g.st->rho;
     const float lb = (g.lam_batch != nullptr) ? g.lam_batch[batch] : 0.0f;
+    const int cnt = half ? fo : ce;
     __syncthreads();   // all waves finished reading the input tile
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (s < nslot) {
-        const int rt = wave + NW * s;
-        const int r0 = rt * 16 + (lane >> 4) * 4;
+        const int r0 = (lw + HW * s) * 16 + (lane >> 4) * 4;   // row within the half
         float sc[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = r0 + r;
-          sc[r] = (row < g.rows) ? rho * rcp_f(rho + g.alpha * (g.lam_row[row] + lb)) : 0.0f;
+          sc[r] = (row < cnt) ? rho * rcp_f(rho + g.alpha * (g.lam_row[half * ce + row] + lb))
+                              : 0.0f;
         }
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
@@ -302,21 +379,24 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
             hv[r] = h;
             lv[r] = l;
           }
-          *reinterpret_cast<u2v*>(&Lhi[col * KP + r0]) = hv;
-          *reinterpret_cast<u2v*>(&Llo[col * KP + r0]) = lv;
+          *reinterpret_cast<u2v*>(&Lhi[col * KP + koff + r0]) = hv;
+          *reinterpret_cast<u2v*>(&Llo[col * KP + koff + r0]) = lv;
           acc[s][ct] = f4{0.f, 0.f, 0.f, 0.f};
         }
       }
     }
     __syncthreads();
-    gemm_bf16<SLOTS, KSM, GemmPD<KSM>::value, NW>(reinterpret_cast<const us8*>(g.A2), frag_stride,
-                                                  g.KS, wave, lane, nslot, Lhi, Llo, KP, acc);
+    gemm_bf16<SLOTS, KSM, GemmPD<KSM>::value>(reinterpret_cast<const us8*>(g.A2), frag_stride,
+                                              g.KS, rt0, HW, lane, nslot, Lhi, Llo, KP, koff, acc);
   }
   __syncthreads();   // the LDS tile is reused for the output
   float* T = reinterpret_cast<float*>(lds_bf);
-  acc_to_lds<SLOTS, NW>(T, acc, wave, lane, nslot);
+  acc_rows_to_lds<SLOTS>(T, acc, rt0, HW, lane, nslot);
   __syncthreads();
-  tile_epilogue<EPI, NW>(g, T, bofs, c0, pslot);
+  if (FUSED || g.dir == 1)
+    tile_epilogue<EPI, NW, OUT_EVEN_ODD>(g, T, bofs, c0, pslot, RTh * 16);
+  else
+    tile_epilogue<EPI, NW, OUT_HALF_ORDER>(g, T, bofs, c0, pslot, RTh * 16);
   __syncthreads();   // LDS free for the next tile
 }
 
@@ -399,7 +479,7 @@ __device__ __forceinline__ void dct_f32_body(const GemmArgs& g, int batch, int c
   __syncthreads();
   acc_to_lds<SLOTS, 4>(lds_f, acc, wave, lane, nslot);
   __syncthreads();
-  tile_epilogue<EPI, 4>(g, lds_f, bofs, c0, pslot);
+  tile_epilogue<EPI, 4, OUT_PLAIN>(g, lds_f, bofs, c0, pslot, 0);
   __syncthreads();
 }
 
@@ -408,7 +488,8 @@ __host__ __device__ inline size_t dct_lds_bytes(int prec, const GemmArgs& g) {
   const size_t out_tile = (size_t)g.RT * 16 * (DCT_NT + 4) * sizeof(float);
   size_t in_tile;
   if (prec == 1) {
-    in_tile = (size_t)2 * DCT_NT * (g.KS * 32 + 8) * sizeof(unsigned short);
+    // hi and lo tiles, both halves of the even/odd split (KS steps of 32 each) + padding
+    in_tile = (size_t)2 * DCT_NT * (2 * g.KS * 32 + 8) * sizeof(unsigned short);
   } else {
     // the fused pass writes back all 16-row tiles, which may exceed the padded contraction
     const int rows = g.KS * 4 > g.RT * 16 ? g.KS * 4 : g.RT * 16;
