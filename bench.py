@@ -376,6 +376,49 @@ def served_leg(dev, seconds, rate, pool_size, max_iter):
     return out
 
 
+def precond_leg(dev, gn_steps=3, applies=5):
+    """The preconditioner comparison of Section 5 on the 128 x 128 x 64 synthetic volume
+    (PE axis 2): for each preconditioner, GN-PCG from b = 0 for a fixed number of steps
+    (PCG iterations per step, wall time) and the device time of one application at the
+    field reached (HIP events around epi_precond_apply, which also evaluates H_JGN)."""
+    import torch
+    from synth import config_volume, CONFIGS
+    from paper_1607_00531_amd import Problem
+    cfg = CONFIGS["3d_128x128x64"]
+    v = config_volume("3d_128x128x64", 0)
+    Ip = torch.tensor(v.Ip, dtype=torch.float32, device=dev)
+    Im = torch.tensor(v.Im, dtype=torch.float32, device=dev)
+    M, m2, m3 = v.m
+    out = {"workload": f"GN-PCG, {m3}x{m2}x{M} cells (canonical), alpha={cfg['alpha']}, "
+                       f"{gn_steps} GN steps from b=0"}
+    with Problem(Ip, Im, v.h, cfg["alpha"], cfg["beta"], precision="mixed") as pr:
+        r = torch.randn(pr.shape_faces, device=dev)
+        z = torch.empty_like(r)
+        for pc in ("block", "jacobi", "sgs", "none"):
+            b = torch.zeros(pr.shape_faces, device=dev)
+            pr.solve_gnpcg(b.clone(), max_iter=1, use_stopping=0, precond=pc)   # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = pr.solve_gnpcg(b, max_iter=gn_steps, use_stopping=0, precond=pc)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            pr.precond_apply(b, r, pc, out=z)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            for _ in range(applies):
+                pr.precond_apply(b, r, pc, out=z)
+            ev[1].record()
+            torch.cuda.synchronize()
+            npcg = sum(rep["pcg_iters"])
+            out[pc] = {"pcg_iters": rep["pcg_iters"], "J": [round(x, 6) for x in rep["J"]],
+                       "gn_wall_s": round(wall, 4),
+                       "ms_per_pcg_iter_incl_gn_overhead": round(1e3 * wall / max(npcg, 1), 3),
+                       "apply_ms_incl_hessian_eval": round(ev[0].elapsed_time(ev[1]) / applies, 3)}
+            log(f"precond {pc}: {json.dumps(out[pc])}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +435,8 @@ def main():
     ap.add_argument("--batch-volumes", type=int, default=48)
     ap.add_argument("--batch-iters", type=int, default=40)
     ap.add_argument("--no-served", action="store_true", help="skip the request-stream leg")
+    ap.add_argument("--no-precond", action="store_true",
+                    help="skip the preconditioner comparison on the 128x128x64 volume")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-pool", type=int, default=24)
@@ -531,6 +576,11 @@ def main():
         log("served leg")
         served = served_leg(dev, args.serve_seconds, args.serve_rate, args.serve_pool, MAX_ITER)
 
+    precond = None
+    if not args.no_precond:
+        log("preconditioner leg")
+        precond = precond_leg(dev)
+
     base = None
     err = None
     if not args.no_cpu_baseline:
@@ -570,6 +620,7 @@ def main():
         "gnpcg": gn,
         "batched": batched,
         "served": served,
+        "preconditioners": precond,
         "cpu_baseline": base,
         "error_vs_oracle": err,
     }

@@ -60,34 +60,50 @@ __device__ __forceinline__ void block_partials(double (&v)[NQ], double* partial,
   }
 }
 
-// Deterministic sum of partial[b*NQ + q] over b in [0, nb) by one 256-thread block;
-// returns the sums to every thread via out_sh (fixed summation order).
-template <int NQ>
+// Deterministic sum of partial[b*NQ + q] over b in [0, nb) by one workgroup of NT threads
+// (a multiple of 64, at most 1024); returns the sums to every thread via out_sh (fixed
+// summation order). Each thread's loads (blocks t, t + NT, ...) are issued before the
+// first add; then one shuffle reduction per wavefront and one barrier.
+template <int NQ, int NT = 256>
 __device__ __forceinline__ void reduce_partials(const double* partial, int nb, double* out_sh) {
-  __shared__ double red[NQ][256];
-  const int t = threadIdx.x;
+  constexpr int NWV = NT / 64;
+  __shared__ double red[NQ][NWV];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  double s[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) s[q] = 0.0;
+  int b = t;
+  for (; b + 3 * NT < nb; b += 4 * NT) {
+    double v[4][NQ];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) v[k][q] = partial[(size_t)(b + NT * k) * NQ + q];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) s[q] += (v[0][q] + v[1][q]) + (v[2][q] + v[3][q]);
+  }
+  {
+    double v[3][NQ];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        v[k][q] = (b + NT * k < nb) ? partial[(size_t)(b + NT * k) * NQ + q] : 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) s[q] += (v[0][q] + v[1][q]) + v[2][q];
+  }
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int b = t;
-    for (; b + 768 < nb; b += 1024) {
-      s0 += partial[(size_t)b * NQ + q];
-      s1 += partial[(size_t)(b + 256) * NQ + q];
-      s2 += partial[(size_t)(b + 512) * NQ + q];
-      s3 += partial[(size_t)(b + 768) * NQ + q];
-    }
-    for (; b < nb; b += 256) s0 += partial[(size_t)b * NQ + q];
-    red[q][t] = (s0 + s1) + (s2 + s3);
+    const double w = wave_sum(s[q]);
+    if (lane == 0) red[q][wave] = w;
   }
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (t < w) {
+  if (t < NQ) {
+    double a = 0.0;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) red[q][t] += red[q][t + w];
-    }
-    __syncthreads();
+    for (int w = 0; w < NWV; ++w) a += red[t][w];
+    out_sh[t] = a;
   }
-  if (t < NQ) out_sh[t] = red[t][0];
   __syncthreads();
 }
 

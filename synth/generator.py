@@ -209,9 +209,12 @@ _POOL_MIN_CELLS = 400_000     # smaller volumes are generated in-process
 
 def _pool_usable() -> bool:
     """Spawned workers re-import the main module: only possible when it is a real file
-    (or absent, as under ``python -c``)."""
+    (or absent, as under ``python -c``). EPI_SYNTH_SERIAL=1 keeps generation in-process
+    (for runs under a profiler, which would follow every worker)."""
     import os
     import sys
+    if os.environ.get("EPI_SYNTH_SERIAL", "0") not in ("", "0"):
+        return False
     f = getattr(sys.modules.get("__main__"), "__file__", None)
     return _threads() > 1 and (f is None or os.path.exists(f))
 
