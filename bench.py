@@ -379,8 +379,10 @@ def served_leg(dev, seconds, rate, pool_size, max_iter):
 def precond_leg(dev, gn_steps=3, applies=5):
     """The preconditioner comparison of Section 5 on the 128 x 128 x 64 synthetic volume
     (PE axis 2): for each preconditioner, GN-PCG from b = 0 for a fixed number of steps
-    (PCG iterations per step, wall time) and the device time of one application at the
-    field reached (HIP events around epi_precond_apply, which also evaluates H_JGN)."""
+    (PCG iterations and final relative residual per step, wall time) and the device time of
+    one application at the field reached (HIP events around epi_precond_apply, which also
+    evaluates H_JGN). Two weights: the volume's alpha, where the transverse smoothness
+    coupling dominates H_JGN, and a data-dominated alpha = 0.5."""
     import torch
     from synth import config_volume, CONFIGS
     from paper_1607_00531_amd import Problem
@@ -389,33 +391,38 @@ def precond_leg(dev, gn_steps=3, applies=5):
     Ip = torch.tensor(v.Ip, dtype=torch.float32, device=dev)
     Im = torch.tensor(v.Im, dtype=torch.float32, device=dev)
     M, m2, m3 = v.m
-    out = {"workload": f"GN-PCG, {m3}x{m2}x{M} cells (canonical), alpha={cfg['alpha']}, "
-                       f"{gn_steps} GN steps from b=0"}
-    with Problem(Ip, Im, v.h, cfg["alpha"], cfg["beta"], precision="mixed") as pr:
-        r = torch.randn(pr.shape_faces, device=dev)
-        z = torch.empty_like(r)
-        for pc in ("block", "jacobi", "sgs", "none"):
-            b = torch.zeros(pr.shape_faces, device=dev)
-            pr.solve_gnpcg(b.clone(), max_iter=1, use_stopping=0, precond=pc)   # warm-up
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rep = pr.solve_gnpcg(b, max_iter=gn_steps, use_stopping=0, precond=pc)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-            pr.precond_apply(b, r, pc, out=z)
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-            torch.cuda.synchronize()
-            ev[0].record()
-            for _ in range(applies):
+    out = {"workload": f"GN-PCG, {m3}x{m2}x{M} cells (canonical), {gn_steps} GN steps from "
+                       f"b=0, eta=0.1, at most 30 PCG iterations per step"}
+    for alpha in (cfg["alpha"], 0.5):
+        res = {}
+        with Problem(Ip, Im, v.h, alpha, cfg["beta"], precision="mixed") as pr:
+            r = torch.randn(pr.shape_faces, device=dev)
+            z = torch.empty_like(r)
+            for pc in ("block", "jacobi", "sgs", "none"):
+                b = torch.zeros(pr.shape_faces, device=dev)
+                pr.solve_gnpcg(b.clone(), max_iter=1, use_stopping=0, precond=pc)   # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rep = pr.solve_gnpcg(b, max_iter=gn_steps, use_stopping=0, precond=pc)
+                torch.cuda.synchronize()
+                wall = time.perf_counter() - t0
                 pr.precond_apply(b, r, pc, out=z)
-            ev[1].record()
-            torch.cuda.synchronize()
-            npcg = sum(rep["pcg_iters"])
-            out[pc] = {"pcg_iters": rep["pcg_iters"], "J": [round(x, 6) for x in rep["J"]],
-                       "gn_wall_s": round(wall, 4),
-                       "ms_per_pcg_iter_incl_gn_overhead": round(1e3 * wall / max(npcg, 1), 3),
-                       "apply_ms_incl_hessian_eval": round(ev[0].elapsed_time(ev[1]) / applies, 3)}
-            log(f"precond {pc}: {json.dumps(out[pc])}")
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                torch.cuda.synchronize()
+                ev[0].record()
+                for _ in range(applies):
+                    pr.precond_apply(b, r, pc, out=z)
+                ev[1].record()
+                torch.cuda.synchronize()
+                npcg = sum(rep["pcg_iters"])
+                res[pc] = {"pcg_iters": rep["pcg_iters"],
+                           "pcg_relres": [round(x, 4) for x in rep["pcg_relres"]],
+                           "J": [round(x, 6) for x in rep["J"]],
+                           "gn_wall_s": round(wall, 4),
+                           "ms_per_pcg_iter_incl_gn_overhead": round(1e3 * wall / max(npcg, 1), 3),
+                           "apply_ms_incl_hessian_eval": round(ev[0].elapsed_time(ev[1]) / applies, 3)}
+                log(f"precond alpha={alpha} {pc}: {json.dumps(res[pc])}")
+        out[f"alpha={alpha}"] = res
     return out
 
 

@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_batch_bstep(BatchDev* bd, int cls) {
   const int nr = T.n;
   if (nr == 0) return;
   const int total = T.first[nr];
-  __shared__ float sbuf[EPI_LINE_WAVES][5][LineBuf<P>::SIZE];
+  __shared__ float sbuf[EPI_LINE_WAVES][LinePad + 5 * LineBuf<P>::SIZE];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int unit = xcd_remap(blockIdx.x, gridDim.x);
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_batch_bstep(BatchDev* bd, int cls) {
   if (st->admm_done) return;
   const int line = gl - T.first[k];
   const bool hard = bstep_line_body<P>(S.la, (float)st->rho, (float)st->u_scale, S.b, S.z, S.u, S.w, line, true,
-                                       &sbuf[wave][0][0], lane, &st->numeric_bad);
+                                       &sbuf[wave][LinePad], lane, &st->numeric_bad);
   if (hard && lane == 0) {
     const int idx = atomicAdd(&bd->hard_count[cls], 1);
     bd->hard_list[cls][idx] = HardItem{slot, line};

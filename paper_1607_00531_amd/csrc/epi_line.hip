@@ -399,12 +399,12 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
                                                     float* __restrict__ wvec, int* hard_list,
                                                     DevState* st) {
   if (st->admm_done) return;
-  __shared__ float sbuf[EPI_LINE_WAVES][5][LineBuf<P>::SIZE];
+  __shared__ float sbuf[EPI_LINE_WAVES][LinePad + 5 * LineBuf<P>::SIZE];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
   const bool hard = bstep_line_body<P>(a, (float)st->rho, (float)st->u_scale, bvec, zvec, uvec, wvec,
-                                       valid ? line : 0, valid, &sbuf[wave][0][0], lane,
+                                       valid ? line : 0, valid, &sbuf[wave][LinePad], lane,
                                        &st->numeric_bad);
   if (valid && hard && lane == 0) {
     const int idx = atomicAdd(&st->hard_count, 1);

@@ -32,6 +32,36 @@ __device__ __forceinline__ void interp_lds(const float* sT, int M, int c, float 
   der = (t1 - t0) * inv_hp;
 }
 
+// The same interpolation from a line whose LDS buffer carries zero samples at the indices
+// -2, -1 and M + 1 (and, as staged, at M .. 64 P - 1): the segment index is clamped into
+// [-2, M], where both end samples are the zero padding, so no selects are needed.
+// sT may be read at lds_pad(-2) = -3 .. lds_pad(M + 1): the caller reserves the 3 floats
+// before the buffer (LinePad).
+__device__ __forceinline__ void interp_lds_z(const float* sT, int M, int c, float disp,
+                                             float inv_hp, float& val, float& der) {
+  disp = fminf(fmaxf(disp, -(float)(2 * M + 4)), (float)(2 * M + 4));
+  const float fl = floorf(disp);
+  const int k = min(max(c + (int)fl, -2), M);
+  const float f = disp - fl;
+  const float t0 = sT[lds_pad(k)], t1 = sT[lds_pad(k + 1)];
+  val = fmaf(f, t1 - t0, t0);
+  der = (t1 - t0) * inv_hp;
+}
+
+// Floats reserved in front of a zero-padded line buffer (lds_pad(-2) = -3).
+constexpr int LinePad = 4;
+
+// Writes the zero padding of interp_lds_z for one staged line (one lane of the wavefront
+// that reads it; LDS accesses of a wavefront are performed in order, so its other lanes see
+// the zeros without a barrier).
+__device__ __forceinline__ void zero_pad_line(float* sT, int M, int lane) {
+  if (lane == 0) {
+    sT[lds_pad(-2)] = 0.0f;
+    sT[lds_pad(-1)] = 0.0f;
+    sT[lds_pad(M + 1)] = 0.0f;
+  }
+}
+
 // Per-cell quantities of the residual for the cells c = P*lane + j (zero for c >= M):
 // g = D1 b, r = I+(x + A b)(1 + g) - I-(x - A b)(1 - g) and the two Jacobian entries
 // dr_c/db_c = Jl, dr_c/db_{c+1} = Jr.
@@ -40,7 +70,7 @@ struct Cells {
   float g[P], r[P], Jl[P], Jr[P];
 };
 
-template <int P>
+template <int P, bool PADDED = false>
 __device__ __forceinline__ void eval_cells(const LineArgs& a, const float (&b)[P],
                                            const float* sIp, const float* sIm, int lane,
                                            Cells<P>& C) {
@@ -53,8 +83,13 @@ __device__ __forceinline__ void eval_cells(const LineArgs& a, const float (&b)[P
     const float aidx = 0.5f * (b[j] + bR) * a.inv_hp;
     const float g = (bR - b[j]) * a.inv_hp;
     float ipv, ipd, imv, imd;
-    interp_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
-    interp_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
+    if (PADDED) {
+      interp_lds_z(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
+      interp_lds_z(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
+    } else {
+      interp_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
+      interp_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
+    }
     const float gp = 1.0f + g, gm = 1.0f - g;
     const float Sd = ipd * gp + imd * gm, Tv = ipv + imv;
     const bool in = c < a.M;
@@ -89,14 +124,14 @@ __device__ __forceinline__ float cross_diag(const LineArgs& a, int jj, int kk) {
 //   G = H_D(b^k) + alpha v D1'D1 + rho v I          (SPD tridiagonal)
 // and the QP  min 1/2 x'Gx + c'x  s.t.  -1 <= D1 (b^k + x) <= 1.
 // ------------------------------------------------------------------------------------
-template <int P>
+template <int P, bool PADDED = false>
 __device__ __forceinline__ void qp_data(const LineArgs& a, float rho, const float (&b)[P],
                                         const float (&z)[P], const float (&u)[P],
                                         const float* sIp, const float* sIm, int lane,
                                         float (&Gd)[P], float (&Go)[P], float (&c)[P],
                                         float (&g)[P]) {
   Cells<P> C;
-  eval_cells<P>(a, b, sIp, sIm, lane, C);
+  eval_cells<P, PADDED>(a, b, sIp, sIm, lane, C);
   float Jrr[P], rpJ[P], gprev[P], JrPrev[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) Jrr[j] = C.Jr[j] * C.r[j];
@@ -129,7 +164,8 @@ __device__ __forceinline__ void qp_data(const LineArgs& a, float rho, const floa
 // unconstrained step -G^{-1} c keeps |D1 b| <= 1 are solved by that single tridiagonal
 // solve (the active-set method terminates there); returns true (wave-uniform) for the
 // other lines, which are left untouched for the active-set path. Writes b^{k+1} (in
-// place) and w = b^{k+1} + u^k. sw: this wave's five LDS line buffers. Every wave of the
+// place) and w = b^{k+1} + u^k. sw: this wave's five LDS line buffers, preceded by LinePad
+// floats that receive the zero padding of the first image line. Every wave of the
 // workgroup must call it (barriers).
 template <int P>
 __device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho, float us,
@@ -144,9 +180,11 @@ __device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho, fl
                           zvec + base, uvec + base};
   const int cnt[5] = {a.M, a.M, NF, NF, NF};
   float v[5][P];
+  float* sIp = sw;
+  float* sIm = sw + LineBuf<P>::SIZE;
   stage_in_n<P, 5>(srcs, cnt, valid, sw, v, lane);
-  const float* sIp = sw;
-  const float* sIm = sw + LineBuf<P>::SIZE;
+  zero_pad_line(sIp, a.M, lane);
+  zero_pad_line(sIm, a.M, lane);
   float b[P], z[P], u[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -155,7 +193,7 @@ __device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho, fl
     u[j] = v[4][j] * us;   // pending rescale of the scaled dual (1 with a fixed rho)
   }
   float Gd[P], Go[P], c[P], g[P];
-  qp_data<P>(a, rho, b, z, u, sIp, sIm, lane, Gd, Go, c, g);
+  qp_data<P, true>(a, rho, b, z, u, sIp, sIm, lane, Gd, Go, c, g);
   float x[P];
   bool hard = false;
 #pragma unroll
