@@ -19,6 +19,11 @@ typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 #define DCT_NT 64          // columns per workgroup
 
+// padding (bfloat16 elements) of a column of the split-bfloat16 LDS tile
+#ifndef EPI_DCT_KPAD
+#define EPI_DCT_KPAD 8
+#endif
+
 // wavefronts per workgroup of the split-bfloat16 tile kernels (float32 kernels use 4)
 #ifndef EPI_DCT_NW
 #define EPI_DCT_NW 8
@@ -270,7 +275,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
   constexpr int NIT = (NG + NW - 1) / NW;
   const int N = g.rows, ce = (N + 1) / 2, fo = N / 2;
   const int KPh = g.KS * 32;                       // contraction extent of one half
-  const int KP = 2 * KPh + 8;
+  const int KP = 2 * KPh + EPI_DCT_KPAD;
   const int RTh = g.RT / 2;
   const bool fwd_in = FUSED || g.dir == 0;
   unsigned short* Lhi = lds_bf;
@@ -489,7 +494,7 @@ __host__ __device__ inline size_t dct_lds_bytes(int prec, const GemmArgs& g) {
   size_t in_tile;
   if (prec == 1) {
     // hi and lo tiles, both halves of the even/odd split (KS steps of 32 each) + padding
-    in_tile = (size_t)2 * DCT_NT * (2 * g.KS * 32 + 8) * sizeof(unsigned short);
+    in_tile = (size_t)2 * DCT_NT * (2 * g.KS * 32 + EPI_DCT_KPAD) * sizeof(unsigned short);
   } else {
     // the fused pass writes back all 16-row tiles, which may exceed the padded contraction
     const int rows = g.KS * 4 > g.RT * 16 ? g.KS * 4 : g.RT * 16;

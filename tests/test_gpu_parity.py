@@ -291,6 +291,36 @@ def test_pcg_counts_per_preconditioner(shape, pe, alpha):
         assert np.abs(N(b) - bo).max() / P.hp <= FIELD_VOX, precond
 
 
+@pytest.mark.parametrize("shape,pe,alpha", [((24, 24), 1, 200.0), ((12, 10, 8), 0, 0.5)])
+def test_preconditioned_spectra(shape, pe, alpha):
+    """The spectra of Section 5 (Figs. 4-6) on a small synthetic problem after three GN
+    steps: the extreme eigenvalues of P^-1 H_JGN with the GPU's block-Jacobi, Jacobi and
+    SGS preconditioners (P^-1 assembled column by column through epi_precond_apply) match
+    those of the oracle's preconditioners within 1e-3 (float32 assembly of P)."""
+    v = generate(3, shape, pe)
+    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
+    b, _ = O.solve_gnpcg(P, max_iter=3, use_stopping=False)
+    tri = O.hessian_tridiag(P, b, True)
+    E = np.eye(P.n)
+    H = np.stack([O.hessian_apply(P, tri, E[i].reshape(P.L, -1)).reshape(-1) for i in range(P.n)], 1)
+    conds = {}
+    with _problem(v, alpha) as pr:
+        sh = pr.shape_faces
+        bt = T(b.reshape(sh))
+        for pc in ("block", "jacobi", "sgs"):
+            Po = np.stack([oracle_precond(P, tri, E[i].reshape(P.L, -1), pc).reshape(-1)
+                           for i in range(P.n)], 1)
+            Pg = np.stack([N(pr.precond_apply(bt, T(E[i].reshape(sh)), pc)).reshape(-1)
+                           for i in range(P.n)], 1)
+            evo = np.sort(np.linalg.eigvals(Po @ H).real)
+            evg = np.sort(np.linalg.eigvals(Pg @ H).real)
+            assert evo[0] > 0
+            for a, c in ((evg[0], evo[0]), (evg[-1], evo[-1])):
+                assert abs(a - c) <= 1e-3 * abs(c), (pc, a, c)
+            conds[pc] = evo[-1] / evo[0]
+    print("cond(P^-1 H):", {k: f"{x:.3g}" for k, x in conds.items()})
+
+
 def test_gnpcg_stopping_rule():
     v = generate(1, (40, 32), 1)
     P = O.make_problem(v.Ip, v.Im, v.h, 0.5)
