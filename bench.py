@@ -45,12 +45,20 @@ def log(*a):
 
 
 def mfma_flops(M, m2, m3, precision):
-    """Matrix-core flops each DCT pass executes (dense products over the unpadded transform
-    lengths; the split-bf16 form runs three products per multiply-add)."""
+    """Matrix-core flops each DCT pass executes over the unpadded transform lengths. The
+    split-bf16 path runs the even/odd halves of each transform (2c^2 + 2f^2 per column of
+    length m, c = ceil(m/2), f = floor(m/2)) with three products per multiply-add; the
+    float32 path runs full products (2m^2 per column)."""
     n = (M + 1) * m2 * m3
-    k = 3 if precision == "mixed" else 1
-    return {"dct_axis3": k * 2 * m3 * n, "dct_axis2_fused": k * 2 * 2 * m2 * n,
-            "dct_last_epilogue": k * 2 * m3 * n}
+
+    def per_face(m):
+        if precision == "mixed":
+            c, f = (m + 1) // 2, m // 2
+            return 3 * (2 * c * c + 2 * f * f) / m
+        return 2 * m
+
+    return {"dct_axis3": per_face(m3) * n, "dct_axis2_fused": 2 * per_face(m2) * n,
+            "dct_last_epilogue": per_face(m3) * n}
 
 
 def algorithmic_bytes(M, m2, m3):
