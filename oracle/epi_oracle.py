@@ -48,7 +48,8 @@ __all__ = [
     "adapt_rho", "RHO_FIXED", "RHO_ADAPT", "RHO_ADAPT_FLOOR",
     "corrected_images", "ncc", "image_quality",
     "coarse_count", "level_sizes", "restrict_cells", "prolong_faces", "feasible",
-    "solve_multilevel_admm",
+    "solve_multilevel_admm", "solve_multilevel_gnpcg", "ml_restart",
+    "ML_RESTART_PROLONG_ALL", "ML_RESTART_FINE_B", "ML_RESTART_AVERAGE",
     "dense_operators",
 ]
 
@@ -915,36 +916,84 @@ def feasible(P: Problem, b, tol=1e-5) -> bool:
     return bool(np.all(np.abs(np.diff(P.lines(b), axis=1)) / P.hp <= 1.0 + tol))
 
 
-def solve_multilevel_admm(Ip, Im, h, alpha, levels=3, beta=10.0, gamma=1e-3, rho=1e3,
-                          **admm):
-    """Coarse-to-fine ADMM (Section 4.4) from b = z = u = 0 on the coarsest level. Between
-    levels: b0 = z0 = (P b + P z) / 2 (the third restart strategy; P = prolongation), taken
-    from (P b + P z) / 2 on the coarse data, u0 = 0; if that average violates |D1 b| <= 1
-    (z is not constrained) b0 = P b instead. rho carries over between levels (the rho of
-    the last iteration). Returns (b on the finest grid, per-level ADMM reports, sizes)."""
+ML_RESTART_PROLONG_ALL, ML_RESTART_FINE_B, ML_RESTART_AVERAGE = 1, 2, 3
+
+
+def ml_restart(P: Problem, strategy: int, bc, zc, uc, mc, mf):
+    """Starting ADMM state (b0, z0, u0) on the finer grid mf from the coarse result
+    (b_c, z_c, u_c) on mc, by the three strategies of Section 4.4:
+      1: b0 = P b_c, z0 = P z_c, u0 = P u_c;
+      2: b0 = z0 = P b_c, u0 = 0;
+      3: b0 = z0 = P((b_c + z_c) / 2), u0 = 0 -- with b0 = P b_c instead when that average
+         violates |D1 b| <= 1 (z is not constrained, so the average may be infeasible).
+    P = prolong_faces; P is the fine Problem (for the feasibility test)."""
+    pb = prolong_faces(bc, mc, mf)
+    if strategy == ML_RESTART_PROLONG_ALL:
+        return pb, prolong_faces(zc, mc, mf), prolong_faces(uc, mc, mf)
+    zero = np.zeros_like(pb)
+    if strategy == ML_RESTART_FINE_B:
+        return pb, pb.copy(), zero
+    if strategy == ML_RESTART_AVERAGE:
+        avg = prolong_faces(0.5 * (bc + zc), mc, mf)
+        return (avg if feasible(P, avg) else pb), avg, zero
+    raise ValueError(strategy)
+
+
+def _ml_problems(Ip, Im, h, alpha, levels, beta, gamma):
+    """(sizes coarse to fine, a function level -> Problem on that level's restricted images)."""
     M, m2, m3 = Ip.shape[2], Ip.shape[1], Ip.shape[0]
     sizes = level_sizes(M, m2, m3, levels)
     imgs = {sizes[-1]: (np.asarray(Ip, np.float64), np.asarray(Im, np.float64))}
     for lf, lc in zip(sizes[::-1][:-1], sizes[::-1][1:]):
         fp, fm = imgs[lf]
         imgs[lc] = (restrict_cells(fp, lf, lc), restrict_cells(fm, lf, lc))
-    reps = []
-    bc = zc = None
-    for li, sz in enumerate(sizes):
+
+    def problem(li):
+        sz = sizes[li]
         hl = tuple(h[a] * (M, m2, m3)[a] / sz[a] for a in range(3))
         if m3 == 1:
             hl = (hl[0], hl[1], h[2])
-        P = make_problem(imgs[sz][0], imgs[sz][1], hl, alpha, beta, gamma)
+        return make_problem(imgs[sz][0], imgs[sz][1], hl, alpha, beta, gamma)
+
+    return sizes, problem
+
+
+def solve_multilevel_admm(Ip, Im, h, alpha, levels=3, beta=10.0, gamma=1e-3, rho=1e3,
+                          restart=ML_RESTART_AVERAGE, **admm):
+    """Coarse-to-fine ADMM (Section 4.4) from b = z = u = 0 on the coarsest level, the
+    finer levels started by ml_restart (the paper's experiments use strategy 3). rho carries
+    over between levels (the rho of the last iteration). Returns (b on the finest grid,
+    per-level ADMM reports, sizes)."""
+    sizes, problem = _ml_problems(Ip, Im, h, alpha, levels, beta, gamma)
+    reps = []
+    bc = zc = uc = None
+    for li, sz in enumerate(sizes):
+        P = problem(li)
         if bc is None:
-            b0 = z0 = np.zeros((sz[2], sz[1], sz[0] + 1))
+            b0 = z0 = u0 = np.zeros((sz[2], sz[1], sz[0] + 1))
         else:
-            avg = prolong_faces(0.5 * (bc + zc), sizes[li - 1], sz)
-            z0 = avg
-            b0 = avg if feasible(P, avg) else prolong_faces(bc, sizes[li - 1], sz)
-        b, z, u, rep = solve_admm(P, b0, z0, np.zeros_like(b0), rho=rho, **admm)
+            b0, z0, u0 = ml_restart(P, restart, bc, zc, uc, sizes[li - 1], sz)
+        b, z, u, rep = solve_admm(P, b0, z0, u0, rho=rho, **admm)
         reps.append(rep)
         rho = rep.rho[-1] if rep.rho else rho
-        bc, zc = b, z
+        bc, zc, uc = b, z, u
+    return bc, reps, sizes
+
+
+def solve_multilevel_gnpcg(Ip, Im, h, alpha, levels=3, beta=10.0, gamma=1e-3, **gn):
+    """Coarse-to-fine GN-PCG (Section 4.4): GN from b = 0 on the coarsest level, each finer
+    level started from the prolongation of the coarser result (feasible: prolongation keeps
+    the coarse D1 b values along PE and mixes lines convexly across). Returns (b on the
+    finest grid, per-level GN reports, sizes)."""
+    sizes, problem = _ml_problems(Ip, Im, h, alpha, levels, beta, gamma)
+    reps = []
+    bc = None
+    for li, sz in enumerate(sizes):
+        P = problem(li)
+        b0 = None if bc is None else prolong_faces(bc, sizes[li - 1], sz)
+        b, rep = solve_gnpcg(P, b0, **gn)
+        reps.append(rep)
+        bc = b
     return bc, reps, sizes
 # ---------------------------------------------------------------------------------------
 def dense_operators(M: int, m2: int, m3: int, hp: float, h2: float, h3: float):

@@ -674,6 +674,70 @@ def test_prolongation_is_exact_on_linear_fields_and_keeps_feasibility():
     assert d1f <= d1c * (1 + 1e-12)
 
 
+def test_single_level_multilevel_is_plain_gn():
+    from synth import generate
+    v = generate(3, (20, 16), 1)
+    b1, reps, sizes = O.solve_multilevel_gnpcg(v.Ip, v.Im, v.h, 0.5, levels=1, max_iter=4,
+                                               use_stopping=False)
+    P = O.make_problem(v.Ip, v.Im, v.h, 0.5)
+    b2, rep = O.solve_gnpcg(P, max_iter=4, use_stopping=False)
+    np.testing.assert_array_equal(b1, b2)
+    assert reps[0].J == rep.J and reps[0].pcg_iters == rep.pcg_iters
+
+
+def test_multilevel_gn_starts_each_level_from_the_prolongated_field():
+    """Section 4.4: the finer level's GN starts at P b_c, so its first objective is the
+    objective of the prolongated coarse result on the finer images, and GN decreases it."""
+    from synth import generate
+    v = generate(4, (24, 20, 8), 0)
+    b, reps, sizes = O.solve_multilevel_gnpcg(v.Ip, v.Im, v.h, 0.5, levels=2, max_iter=3,
+                                              use_stopping=False)
+    assert sizes == [(12, 10, 4), (24, 20, 8)]
+    Pf = O.make_problem(v.Ip, v.Im, v.h, 0.5)
+    Pc = O.make_problem(O.restrict_cells(v.Ip, sizes[1], sizes[0]),
+                        O.restrict_cells(v.Im, sizes[1], sizes[0]),
+                        tuple(2.0 * x for x in v.h), 0.5)
+    coarse_b = O.solve_gnpcg(Pc, max_iter=3, use_stopping=False)[0]
+    start = O.prolong_faces(coarse_b, sizes[0], sizes[1])
+    assert O.feasible(Pf, start)
+    assert reps[1].J[0] == pytest.approx(O.objective(Pf, start, True)["J"], rel=1e-12)
+    assert reps[1].J[-1] < reps[1].J[0] and reps[0].J[-1] < reps[0].J[0]
+
+
+def test_admm_restart_strategies():
+    """The three restarts of Section 4.4 on a coarse state: (1) prolongates b, z and u;
+    (2) b0 = z0 = P b_c, u0 = 0; (3) b0 = z0 = P((b_c + z_c)/2), u0 = 0, falling back to
+    b0 = P b_c when the average leaves the feasible set. Prolongation keeps a feasible b
+    feasible (the fine D1 b values are convex combinations of coarse ones)."""
+    from synth import generate
+    v = generate(5, (16, 12, 8), 0)
+    mf, mc = (16, 12, 8), (8, 6, 4)
+    Pf = O.make_problem(v.Ip, v.Im, v.h, 0.5)
+    r = np.random.default_rng(6)
+    shape_c = (mc[2], mc[1], mc[0] + 1)
+    bc = np.cumsum(r.uniform(-0.9, 0.9, size=shape_c) * (1.0 / mc[0]), axis=2)
+    zc = bc + 0.01 * r.normal(size=shape_c) / mc[0]
+    uc = r.normal(size=shape_c)
+    hc = 1.0 / mc[0]
+    assert np.abs(np.diff(bc, axis=2)).max() / hc <= 0.9
+    b1, z1, u1 = O.ml_restart(Pf, 1, bc, zc, uc, mc, mf)
+    assert np.abs(np.diff(b1, axis=2)).max() / Pf.hp <= np.abs(np.diff(bc, axis=2)).max() / hc + 1e-12
+    assert np.abs(u1).max() > 0 and np.all(z1 != b1)
+    b2, z2, u2 = O.ml_restart(Pf, 2, bc, zc, uc, mc, mf)
+    np.testing.assert_array_equal(b2, b1)
+    np.testing.assert_array_equal(z2, b2)
+    assert not np.any(u2)
+    b3, z3, u3 = O.ml_restart(Pf, 3, bc, zc, uc, mc, mf)
+    np.testing.assert_allclose(z3, 0.5 * (b1 + z1), rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(b3, z3)
+    assert not np.any(u3)
+    steep = zc.copy()
+    steep[..., 1:] += np.arange(1, mc[0] + 1) * 4.0 * hc     # slopes beyond 1 in z only
+    b4, z4, _ = O.ml_restart(Pf, 3, bc, steep, uc, mc, mf)
+    assert not O.feasible(Pf, z4)
+    np.testing.assert_array_equal(b4, b1)
+
+
 def test_single_level_multilevel_is_plain_admm():
     from synth import generate
     v = generate(2, (20, 16), 1)
