@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define EPI_ABI_VERSION 3
+#define EPI_ABI_VERSION 4
 
 typedef enum {
   EPI_OK = 0,
@@ -243,26 +243,44 @@ epi_status epi_prolong_faces(const int32_t m_coarse[3], const int32_t m_fine[3],
 
 #define EPI_ML_MAX_LEVELS 8
 
-/* Per-level outcome of epi_solve_multilevel_admm (index 0 = coarsest level). fallback[l] = 1
- * if the restart average violated |D1 b| <= 1 and b0 = P b_c was used instead. */
+/* Per-level outcome of a multilevel solve (index 0 = coarsest level). ADMM: iterations,
+ * convergence, fallback[l] = 1 if the third restart's average violated |D1 b| <= 1 and
+ * b0 = P b_c was used instead, rho of the last iteration. GN-PCG: GN steps, convergence and
+ * the final J_GN of the level (J_last). */
 typedef struct {
   int32_t levels;
   int32_t m[EPI_ML_MAX_LEVELS][3];
   int32_t iters[EPI_ML_MAX_LEVELS], converged[EPI_ML_MAX_LEVELS], fallback[EPI_ML_MAX_LEVELS];
   double rho_last[EPI_ML_MAX_LEVELS];
+  double J_last[EPI_ML_MAX_LEVELS];
 } epi_ml_report;
+
+/* How ADMM restarts on a finer level from the coarse result (b_c, z_c, u_c), the three
+ * strategies of Section 4.4 (P = epi_prolong_faces): PROLONG_ALL: b0 = P b_c, z0 = P z_c,
+ * u0 = P u_c; FINE_B: b0 = z0 = P b_c, u0 = 0; AVERAGE (the paper's choice):
+ * b0 = z0 = P((b_c + z_c) / 2), u0 = 0, with b0 = P b_c if that average is infeasible. */
+enum { EPI_ML_RESTART_PROLONG_ALL = 1, EPI_ML_RESTART_FINE_B = 2, EPI_ML_RESTART_AVERAGE = 3 };
 
 /* Coarse-to-fine ADMM (Section 4.4) for the image pair of grid (the finest level): up to
  * `levels` levels, every axis with an even count >= 4 halved per level (fewer levels when
  * no axis can be halved), images restricted level by level, ADMM from b = z = u = 0 on the
- * coarsest level with opts; between levels b0 = z0 = P((b_c + z_c) / 2) and u0 = 0 (the
- * third restart strategy of Section 4.4), with b0 = P b_c if that average is infeasible;
- * rho carries over between levels. The finest field is written to d_b (n floats,
- * caller-owned). Allocates and frees the coarse levels' memory; synchronises stream. */
+ * coarsest level with opts, each finer level started by `restart` (an EPI_ML_RESTART_*
+ * value); rho carries over between levels. The finest field is written to d_b (n floats,
+ * caller-owned). Allocates and frees the coarse levels' memory; synchronises stream.
+ * EPI_EINVAL for levels outside [1, EPI_ML_MAX_LEVELS] or an unknown restart. */
 epi_status epi_solve_multilevel_admm(const epi_grid* grid, const float* d_Iplus,
-                                     const float* d_Iminus, int32_t levels,
+                                     const float* d_Iminus, int32_t levels, int32_t restart,
                                      const epi_admm_opts* opts, void* stream, float* d_b,
                                      epi_ml_report* rep);
+
+/* Coarse-to-fine GN-PCG (Section 4.4: the prolongated coarse field is the finer level's
+ * starting guess): GN-PCG with opts from b = 0 on the coarsest level, then from
+ * P b_c on each finer level (feasible: prolongation keeps the coarse D1 b values along PE
+ * and mixes lines convexly across). Levels and memory as for epi_solve_multilevel_admm. */
+epi_status epi_solve_multilevel_gnpcg(const epi_grid* grid, const float* d_Iplus,
+                                      const float* d_Iminus, int32_t levels,
+                                      const epi_gn_opts* opts, void* stream, float* d_b,
+                                      epi_ml_report* rep);
 
 /* The same solve as epi_solve_admm (same kernels in the same order, same results),
  * launched one kernel at a time without the captured graph, with a pair of HIP events

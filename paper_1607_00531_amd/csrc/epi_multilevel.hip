@@ -177,78 +177,125 @@ EPI_API epi_status epi_prolong_faces(const int32_t m_coarse[3], const int32_t m_
 
 static int ml_coarse(int m) { return (m % 2 == 0 && m >= 4) ? m / 2 : m; }
 
+namespace {
+
+// Level sizes (coarse to fine) and the restricted image pairs of one multilevel solve.
+struct MLHierarchy {
+  std::vector<std::array<int, 3>> sizes;
+  std::vector<float*> Ip, Im;   // level l images (the finest level borrows the caller's)
+  int nl = 0;
+
+  epi_status build(const epi_grid* grid, const float* d_Iplus, const float* d_Iminus,
+                   int levels, hipStream_t s) {
+    sizes.assign(1, {grid->m[0], grid->m[1], grid->m[2]});
+    while ((int)sizes.size() < levels) {
+      const auto& l = sizes.back();
+      std::array<int, 3> c{ml_coarse(l[0]), ml_coarse(l[1]), l[2] > 1 ? ml_coarse(l[2]) : 1};
+      if (c == l) break;
+      sizes.push_back(c);
+    }
+    std::reverse(sizes.begin(), sizes.end());
+    nl = (int)sizes.size();
+    Ip.assign(nl, nullptr);
+    Im.assign(nl, nullptr);
+    Ip[nl - 1] = const_cast<float*>(d_Iplus);
+    Im[nl - 1] = const_cast<float*>(d_Iminus);
+    for (int l = nl - 2; l >= 0; --l) {   // fine to coarse
+      hipError_t e = hipMalloc(&Ip[l], ncell(l) * sizeof(float));
+      if (e == hipSuccess) e = hipMalloc(&Im[l], ncell(l) * sizeof(float));
+      if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? EPI_ENOMEM : EPI_EHIP, "level images: %s",
+                    hipGetErrorString(e));
+      int32_t mf[3] = {sizes[l + 1][0], sizes[l + 1][1], sizes[l + 1][2]};
+      int32_t mc[3] = {sizes[l][0], sizes[l][1], sizes[l][2]};
+      epi_status st = epi_restrict_cells(mf, mc, Ip[l + 1], Ip[l], s);
+      if (st == EPI_OK) st = epi_restrict_cells(mf, mc, Im[l + 1], Im[l], s);
+      if (st != EPI_OK) return st;
+    }
+    return EPI_OK;
+  }
+  size_t ncell(int l) const { return (size_t)sizes[l][0] * sizes[l][1] * sizes[l][2]; }
+  size_t nface(int l) const { return (size_t)(sizes[l][0] + 1) * sizes[l][1] * sizes[l][2]; }
+  // the grid of level l: same domain, h scaled with the cell counts
+  epi_grid grid(const epi_grid* fine, int l) const {
+    epi_grid g = *fine;
+    for (int a = 0; a < 3; ++a) {
+      g.m[a] = sizes[l][a];
+      if (!(a == 2 && fine->m[2] == 1)) g.h[a] = fine->h[a] * fine->m[a] / sizes[l][a];
+    }
+    return g;
+  }
+  epi_status prolong(int l, const float* coarse, float* fine, hipStream_t s) const {
+    int32_t mc[3] = {sizes[l - 1][0], sizes[l - 1][1], sizes[l - 1][2]};
+    int32_t mf[3] = {sizes[l][0], sizes[l][1], sizes[l][2]};
+    return epi_prolong_faces(mc, mf, coarse, fine, s);
+  }
+  ~MLHierarchy() {
+    for (int l = 0; l < nl - 1; ++l) {
+      if (Ip[l]) (void)hipFree(Ip[l]);
+      if (Im[l]) (void)hipFree(Im[l]);
+    }
+  }
+};
+
+}  // namespace
+
 EPI_API epi_status epi_solve_multilevel_admm(const epi_grid* grid, const float* d_Iplus,
                                              const float* d_Iminus, int32_t levels,
-                                             const epi_admm_opts* opts, void* stream,
-                                             float* d_b, epi_ml_report* rep) {
+                                             int32_t restart, const epi_admm_opts* opts,
+                                             void* stream, float* d_b, epi_ml_report* rep) {
   if (!grid || !d_Iplus || !d_Iminus || !opts || !d_b) return fail(EPI_EINVAL, "null argument");
   if (levels < 1 || levels > EPI_ML_MAX_LEVELS)
     return fail(EPI_EINVAL, "levels must be in [1, %d]", EPI_ML_MAX_LEVELS);
+  if (restart < EPI_ML_RESTART_PROLONG_ALL || restart > EPI_ML_RESTART_AVERAGE)
+    return fail(EPI_EINVAL, "unknown restart strategy %d", restart);
   epi_status st = validate_grid(grid);
   if (st != EPI_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-
-  // level sizes, coarse to fine
-  std::vector<std::array<int, 3>> sizes{{grid->m[0], grid->m[1], grid->m[2]}};
-  while ((int)sizes.size() < levels) {
-    const auto& l = sizes.back();
-    std::array<int, 3> c{ml_coarse(l[0]), ml_coarse(l[1]), l[2] > 1 ? ml_coarse(l[2]) : 1};
-    if (c == l) break;
-    sizes.push_back(c);
-  }
-  std::reverse(sizes.begin(), sizes.end());
-  const int nl = (int)sizes.size();
-  auto ncell = [](const std::array<int, 3>& m) { return (size_t)m[0] * m[1] * m[2]; };
-  auto nface = [](const std::array<int, 3>& m) { return (size_t)(m[0] + 1) * m[1] * m[2]; };
-
-  std::vector<float*> Ip(nl, nullptr), Im(nl, nullptr);
-  float *bc = nullptr, *zc = nullptr, *tmp = nullptr, *z = nullptr, *u = nullptr, *bl = nullptr;
+  MLHierarchy H;
+  float *bc = nullptr, *zc = nullptr, *uc = nullptr, *tmp = nullptr, *z = nullptr, *u = nullptr,
+        *bl = nullptr;
   int* d_count = nullptr;
   epi_problem* prob = nullptr;
   double rho = opts->rho;
-  Ip[nl - 1] = const_cast<float*>(d_Iplus);
-  Im[nl - 1] = const_cast<float*>(d_Iminus);
-  if (rep) {
-    memset(rep, 0, sizeof(*rep));
-    rep->levels = nl;
-  }
+  int nl = 0;
+  if (rep) memset(rep, 0, sizeof(*rep));
+  if ((st = H.build(grid, d_Iplus, d_Iminus, levels, s)) != EPI_OK) goto done;
+  nl = H.nl;
+  if (rep) rep->levels = nl;
   MLCHK(hipMalloc(&d_count, sizeof(int)));
-  // images of the coarser levels, fine to coarse
-  for (int l = nl - 2; l >= 0; --l) {
-    MLCHK(hipMalloc(&Ip[l], ncell(sizes[l]) * sizeof(float)));
-    MLCHK(hipMalloc(&Im[l], ncell(sizes[l]) * sizeof(float)));
-    int32_t mf[3] = {sizes[l + 1][0], sizes[l + 1][1], sizes[l + 1][2]};
-    int32_t mc[3] = {sizes[l][0], sizes[l][1], sizes[l][2]};
-    if ((st = epi_restrict_cells(mf, mc, Ip[l + 1], Ip[l], s)) != EPI_OK) goto done;
-    if ((st = epi_restrict_cells(mf, mc, Im[l + 1], Im[l], s)) != EPI_OK) goto done;
-  }
   for (int l = 0; l < nl; ++l) {
-    const auto& m = sizes[l];
-    const size_t nf = nface(m);
-    epi_grid g = *grid;
-    for (int a = 0; a < 3; ++a) {
-      g.m[a] = m[a];
-      if (!(a == 2 && grid->m[2] == 1)) g.h[a] = grid->h[a] * grid->m[a] / m[a];
-    }
-    if ((st = epi_setup(&g, Ip[l], Im[l], s, &prob)) != EPI_OK) goto done;
+    const auto& m = H.sizes[l];
+    const size_t nf = H.nface(l);
+    const epi_grid g = H.grid(grid, l);
+    if ((st = epi_setup(&g, H.Ip[l], H.Im[l], s, &prob)) != EPI_OK) goto done;
     bl = (l == nl - 1) ? d_b : nullptr;
     if (!bl) MLCHK(hipMalloc(&bl, nf * sizeof(float)));
     MLCHK(hipMalloc(&z, nf * sizeof(float)));
     MLCHK(hipMalloc(&u, nf * sizeof(float)));
-    MLCHK(hipMemsetAsync(u, 0, nf * sizeof(float), s));
     if (l == 0) {
       MLCHK(hipMemsetAsync(bl, 0, nf * sizeof(float), s));
       MLCHK(hipMemsetAsync(z, 0, nf * sizeof(float), s));
+      MLCHK(hipMemsetAsync(u, 0, nf * sizeof(float), s));
+    } else if (restart == EPI_ML_RESTART_PROLONG_ALL) {
+      // b0 = P b_c, z0 = P z_c, u0 = P u_c
+      if ((st = H.prolong(l, bc, bl, s)) != EPI_OK) goto done;
+      if ((st = H.prolong(l, zc, z, s)) != EPI_OK) goto done;
+      if ((st = H.prolong(l, uc, u, s)) != EPI_OK) goto done;
+    } else if (restart == EPI_ML_RESTART_FINE_B) {
+      // b0 = z0 = P b_c, u0 = 0
+      if ((st = H.prolong(l, bc, bl, s)) != EPI_OK) goto done;
+      MLCHK(hipMemcpyAsync(z, bl, nf * sizeof(float), hipMemcpyDeviceToDevice, s));
+      MLCHK(hipMemsetAsync(u, 0, nf * sizeof(float), s));
     } else {
-      // b0 = z0 = P((b_c + z_c) / 2); b0 = P b_c if the average violates |D1 b| <= 1
-      const auto& mcs = sizes[l - 1];
-      const size_t ncf = nface(mcs);
-      int32_t mcc[3] = {mcs[0], mcs[1], mcs[2]}, mff[3] = {m[0], m[1], m[2]};
+      // b0 = z0 = P((b_c + z_c) / 2), u0 = 0; b0 = P b_c if the average violates |D1 b| <= 1
+      const size_t ncf = H.nface(l - 1);
       MLCHK(hipMalloc(&tmp, ncf * sizeof(float)));
       hipLaunchKernelGGL(k_average, dim3(ml_blocks((long long)ncf)), dim3(256), 0, s, bc, zc, tmp,
                          (long long)ncf);
-      if ((st = epi_prolong_faces(mcc, mff, tmp, z, s)) != EPI_OK) goto done;
+      if ((st = H.prolong(l, tmp, z, s)) != EPI_OK) goto done;
       MLCHK(hipMemcpyAsync(bl, z, nf * sizeof(float), hipMemcpyDeviceToDevice, s));
+      MLCHK(hipMemsetAsync(u, 0, nf * sizeof(float), s));
       MLCHK(hipMemsetAsync(d_count, 0, sizeof(int), s));
       const long long nce = (long long)m[0] * m[1] * m[2];
       hipLaunchKernelGGL(k_violations, dim3(ml_blocks(nce)), dim3(256), 0, s, bl, m[0],
@@ -256,13 +303,17 @@ EPI_API epi_status epi_solve_multilevel_admm(const epi_grid* grid, const float* 
       int count = 0;
       MLCHK(hipMemcpyAsync(&count, d_count, sizeof(int), hipMemcpyDeviceToHost, s));
       MLCHK(hipStreamSynchronize(s));
-      if (count > 0 && (st = epi_prolong_faces(mcc, mff, bc, bl, s)) != EPI_OK) goto done;
+      if (count > 0 && (st = H.prolong(l, bc, bl, s)) != EPI_OK) goto done;
       MLCHK(hipFree(tmp));
       tmp = nullptr;
+      if (rep) rep->fallback[l] = count > 0;
+    }
+    if (l > 0) {
+      MLCHK(hipStreamSynchronize(s));
       MLCHK(hipFree(bc));
       MLCHK(hipFree(zc));
-      bc = zc = nullptr;
-      if (rep) rep->fallback[l] = count > 0;
+      MLCHK(hipFree(uc));
+      bc = zc = uc = nullptr;
     }
     {
       epi_admm_opts o = *opts;
@@ -282,27 +333,91 @@ EPI_API epi_status epi_solve_multilevel_admm(const epi_grid* grid, const float* 
     }
     epi_destroy(prob);
     prob = nullptr;
-    MLCHK(hipFree(u));
-    u = nullptr;
     if (l < nl - 1) {
       bc = bl;
       zc = z;
+      uc = u;
     } else {
+      MLCHK(hipStreamSynchronize(s));
       MLCHK(hipFree(z));
+      MLCHK(hipFree(u));
     }
     bl = nullptr;
-    z = nullptr;
+    z = u = nullptr;
   }
   MLCHK(hipStreamSynchronize(s));
 done:
   if (prob) epi_destroy(prob);
-  for (int l = 0; l < nl - 1; ++l) {
-    if (Ip[l]) (void)hipFree(Ip[l]);
-    if (Im[l]) (void)hipFree(Im[l]);
-  }
-  void* rest[] = {bc, zc, tmp, z, u, d_count};
+  if (s) (void)hipStreamSynchronize(s);
+  void* rest[] = {bc, zc, uc, tmp, z, u, d_count};
   for (void* p : rest)
     if (p) (void)hipFree(p);
+  if (bl && bl != d_b) (void)hipFree(bl);
+  return st;
+}
+
+EPI_API epi_status epi_solve_multilevel_gnpcg(const epi_grid* grid, const float* d_Iplus,
+                                              const float* d_Iminus, int32_t levels,
+                                              const epi_gn_opts* opts, void* stream,
+                                              float* d_b, epi_ml_report* rep) {
+  if (!grid || !d_Iplus || !d_Iminus || !opts || !d_b) return fail(EPI_EINVAL, "null argument");
+  if (levels < 1 || levels > EPI_ML_MAX_LEVELS)
+    return fail(EPI_EINVAL, "levels must be in [1, %d]", EPI_ML_MAX_LEVELS);
+  epi_status st = validate_grid(grid);
+  if (st != EPI_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  MLHierarchy H;
+  float *bc = nullptr, *bl = nullptr;
+  epi_problem* prob = nullptr;
+  int nl = 0;
+  if (rep) memset(rep, 0, sizeof(*rep));
+  if ((st = H.build(grid, d_Iplus, d_Iminus, levels, s)) != EPI_OK) goto done;
+  nl = H.nl;
+  if (rep) rep->levels = nl;
+  for (int l = 0; l < nl; ++l) {
+    const size_t nf = H.nface(l);
+    const epi_grid g = H.grid(grid, l);
+    if ((st = epi_setup(&g, H.Ip[l], H.Im[l], s, &prob)) != EPI_OK) goto done;
+    bl = (l == nl - 1) ? d_b : nullptr;
+    if (!bl) MLCHK(hipMalloc(&bl, nf * sizeof(float)));
+    if (l == 0) {
+      MLCHK(hipMemsetAsync(bl, 0, nf * sizeof(float), s));
+    } else {
+      // b0 = P b_c (feasible when b_c is: prolongation keeps the coarse D1 b values)
+      if ((st = H.prolong(l, bc, bl, s)) != EPI_OK) goto done;
+      MLCHK(hipStreamSynchronize(s));
+      MLCHK(hipFree(bc));
+      bc = nullptr;
+    }
+    {
+      const int n1 = std::max(opts->max_iter, 0) + 1;
+      std::vector<double> J(n1), gn(n1), rel(n1), stp(n1);
+      std::vector<int32_t> pcg(n1);
+      epi_gn_report r{};
+      r.J = J.data();
+      r.grad_norm = gn.data();
+      r.pcg_relres = rel.data();
+      r.step = stp.data();
+      r.pcg_iters = pcg.data();
+      st = epi_solve_gnpcg(prob, bl, opts, &r);
+      if (st != EPI_OK) goto done;
+      if (rep) {
+        for (int a = 0; a < 3; ++a) rep->m[l][a] = H.sizes[l][a];
+        rep->iters[l] = r.iters;
+        rep->converged[l] = r.converged;
+        rep->J_last[l] = J[r.iters];
+      }
+    }
+    epi_destroy(prob);
+    prob = nullptr;
+    if (l < nl - 1) bc = bl;
+    bl = nullptr;
+  }
+  MLCHK(hipStreamSynchronize(s));
+done:
+  if (prob) epi_destroy(prob);
+  if (s) (void)hipStreamSynchronize(s);
+  if (bc) (void)hipFree(bc);
   if (bl && bl != d_b) (void)hipFree(bl);
   return st;
 }

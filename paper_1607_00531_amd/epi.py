@@ -54,7 +54,7 @@ class GNReport(C.Structure):
 
 # penalty strategies of epi_admm_opts.rho_mode
 RHO_MODES = {"fixed": 0, "adapt": 1, "adapt_floor": 2}
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class ADMMOpts(C.Structure):
@@ -333,7 +333,11 @@ ML_MAX_LEVELS = 8
 class MLReport(C.Structure):
     _fields_ = [("levels", C.c_int32), ("m", (C.c_int32 * 3) * ML_MAX_LEVELS),
                 ("iters", C.c_int32 * ML_MAX_LEVELS), ("converged", C.c_int32 * ML_MAX_LEVELS),
-                ("fallback", C.c_int32 * ML_MAX_LEVELS), ("rho_last", C.c_double * ML_MAX_LEVELS)]
+                ("fallback", C.c_int32 * ML_MAX_LEVELS), ("rho_last", C.c_double * ML_MAX_LEVELS),
+                ("J_last", C.c_double * ML_MAX_LEVELS)]
+
+
+ML_RESTARTS = {"prolong_all": 1, "fine_b": 2, "average": 3}
 
 
 def _ml_sigs(L):
@@ -344,9 +348,12 @@ def _ml_sigs(L):
     L.epi_restrict_cells.restype = C.c_int
     L.epi_prolong_faces.argtypes = [i3, i3, vp, vp, vp]
     L.epi_prolong_faces.restype = C.c_int
-    L.epi_solve_multilevel_admm.argtypes = [C.POINTER(Grid), vp, vp, C.c_int32,
+    L.epi_solve_multilevel_admm.argtypes = [C.POINTER(Grid), vp, vp, C.c_int32, C.c_int32,
                                             C.POINTER(ADMMOpts), vp, vp, C.POINTER(MLReport)]
     L.epi_solve_multilevel_admm.restype = C.c_int
+    L.epi_solve_multilevel_gnpcg.argtypes = [C.POINTER(Grid), vp, vp, C.c_int32,
+                                             C.POINTER(GNOpts), vp, vp, C.POINTER(MLReport)]
+    L.epi_solve_multilevel_gnpcg.restype = C.c_int
     L._ml_sigs = True
     return L
 
@@ -374,8 +381,10 @@ def prolong_faces(coarse, fine, stream=None):
 
 
 def solve_multilevel_admm(Ip, Im, h, alpha, b, levels=3, beta=10.0, gamma=1e-3,
-                          precision="mixed", ndim=None, stream=None, **opts) -> dict:
-    """Coarse-to-fine ADMM (epi_solve_multilevel_admm); writes the finest field into b."""
+                          precision="mixed", ndim=None, stream=None, restart="average",
+                          **opts) -> dict:
+    """Coarse-to-fine ADMM (epi_solve_multilevel_admm); writes the finest field into b.
+    restart: "prolong_all", "fine_b" or "average" (the three strategies of Section 4.4)."""
     L = _ml_sigs(lib())
     g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, precision, ndim)
     o = ADMMOpts()
@@ -384,13 +393,37 @@ def solve_multilevel_admm(Ip, Im, h, alpha, b, levels=3, beta=10.0, gamma=1e-3,
         setattr(o, k, RHO_MODES[v] if k == "rho_mode" and isinstance(v, str) else v)
     if tuple(b.shape) != (Ip.shape[0], Ip.shape[1], Ip.shape[2] + 1):
         raise ValueError("b must have the PE-face shape of the images")
+    rs = ML_RESTARTS[restart] if isinstance(restart, str) else int(restart)
     rep = MLReport()
-    _check(L.epi_solve_multilevel_admm(C.byref(g), _ptr(Ip), _ptr(Im), int(levels), C.byref(o),
-                                       _stream_handle(stream), _ptr(b), C.byref(rep)))
+    _check(L.epi_solve_multilevel_admm(C.byref(g), _ptr(Ip), _ptr(Im), int(levels), rs,
+                                       C.byref(o), _stream_handle(stream), _ptr(b),
+                                       C.byref(rep)))
     n = rep.levels
     return dict(levels=n, sizes=[tuple(rep.m[l]) for l in range(n)],
                 iters=list(rep.iters[:n]), converged=[bool(x) for x in rep.converged[:n]],
                 fallback=[bool(x) for x in rep.fallback[:n]], rho_last=list(rep.rho_last[:n]))
+
+
+def solve_multilevel_gnpcg(Ip, Im, h, alpha, b, levels=3, beta=10.0, gamma=1e-3,
+                           precision="mixed", ndim=None, stream=None, **opts) -> dict:
+    """Coarse-to-fine GN-PCG (epi_solve_multilevel_gnpcg); writes the finest field into b."""
+    L = _ml_sigs(lib())
+    g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, precision, ndim)
+    o = GNOpts()
+    L.epi_gn_default_opts(C.byref(o))
+    for k, v in opts.items():
+        if k == "precond":
+            v = PRECOND[v] if isinstance(v, str) else int(v)
+        setattr(o, k, v)
+    if tuple(b.shape) != (Ip.shape[0], Ip.shape[1], Ip.shape[2] + 1):
+        raise ValueError("b must have the PE-face shape of the images")
+    rep = MLReport()
+    _check(L.epi_solve_multilevel_gnpcg(C.byref(g), _ptr(Ip), _ptr(Im), int(levels), C.byref(o),
+                                        _stream_handle(stream), _ptr(b), C.byref(rep)))
+    n = rep.levels
+    return dict(levels=n, sizes=[tuple(rep.m[l]) for l in range(n)],
+                iters=list(rep.iters[:n]), converged=[bool(x) for x in rep.converged[:n]],
+                J_last=list(rep.J_last[:n]))
 
 
 EPI_EBUSY = 7
