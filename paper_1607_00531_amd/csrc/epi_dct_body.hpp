@@ -49,6 +49,9 @@ template <typename T>
 __device__ __forceinline__ void st_at(void* base, unsigned boff, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
+__device__ __forceinline__ void st_stream_at(float* base, unsigned boff, float v) {
+  store_stream(reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff), v);
+}
 
 // Tile index -> (batch, first column), walking each XCD over a contiguous range.
 __device__ __forceinline__ int dct_tile(const GemmArgs& g, int& batch, int& c0) {
@@ -109,7 +112,7 @@ __device__ __forceinline__ void tile_epilogue(const GemmArgs& g, const float* T,
   if (EPI == 0) {
     float* ob = g.out + bofs + c0;
     for (int row = r0; row < g.rows; row += RS)
-      if (cok) st_at<float>(ob + (size_t)row * g.ld, col4, tile_value<OUT>(T, row, col, g.rows, hrow));
+      if (cok) st_stream_at(ob + (size_t)row * g.ld, col4, tile_value<OUT>(T, row, col, g.rows, hrow));
   } else {
     // U rows per thread in flight: all their loads are issued before the first store
     // (the stores to z and u could alias the loads as far as the compiler knows)
