@@ -1,0 +1,45 @@
+"""Host-side parts of bench.py (no GPU): the one-GPU guard, the byte and flop accounting,
+and the counter-summary lookup that keys on the kernel sources."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_algorithmic_bytes_of_the_admm_kernels():
+    import bench
+    M, m2, m3 = 240, 200, 110
+    n, N = (M + 1) * m2 * m3, M * m2 * m3
+    b = bench.algorithmic_bytes(M, m2, m3)
+    assert b["bstep"] == 4 * (2 * N + 5 * n) == 148_280_000
+    assert b["dct_axis3"] == b["dct_axis2_fused"] == 8 * n
+    assert b["dct_last_epilogue"] == 24 * n
+
+
+def test_mfma_flops_of_the_split_transform():
+    """Even/odd halves: 2c^2 + 2f^2 per column of length m (c, f the half lengths), three
+    products per multiply-add in mixed precision; full 2m^2 per column in float32."""
+    import bench
+    M, m2, m3 = 240, 200, 110
+    n = (M + 1) * m2 * m3
+    mixed, fp32 = bench.mfma_flops(M, m2, m3, "mixed"), bench.mfma_flops(M, m2, m3, "fp32")
+    assert mixed["dct_axis3"] == 3 * (2 * 55 * 55 * 2) / 110 * n
+    assert mixed["dct_axis2_fused"] == 2 * 3 * (2 * 100 * 100 * 2) / 200 * n
+    assert fp32["dct_axis2_fused"] == 2 * 2 * m2 * n
+    odd = bench.mfma_flops(10, 7, 5, "mixed")        # odd lengths: c = 4, f = 3 for m = 7
+    assert odd["dct_axis2_fused"] == 2 * 3 * (2 * 16 + 2 * 9) / 7 * (11 * 7 * 5)
+
+
+def test_counter_traffic_keys_on_the_kernel_sources():
+    import bench
+    t = bench.counter_traffic("bstep")
+    assert t is None or t > bench.algorithmic_bytes(240, 200, 110)["bstep"] * 0.9
+    assert bench.counter_traffic("no_such_kernel") is None
