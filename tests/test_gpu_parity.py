@@ -27,7 +27,7 @@ def _smooth_field(P, seed, gmax):
 # shapes (caller order, PE axis) chosen to cover 1..8 faces per lane, ragged tiles, m2 = 1
 SHAPES = [((32, 40), 1), ((16, 20, 12), 0), ((64, 64), 1), ((240, 8, 6), 0),
           ((20, 70, 9), 1), ((3, 130, 5), 1), ((300, 3, 2), 0), ((350, 2, 2), 0),
-          ((420, 2, 3), 0), ((511, 4, 3), 0), ((2, 9, 1), 1)]
+          ((420, 2, 3), 0), ((511, 4, 3), 0), ((2, 9, 1), 1), ((63, 5, 4), 0), ((255, 3, 2), 0)]
 
 
 @pytest.mark.parametrize("shape,pe", SHAPES)
@@ -81,7 +81,11 @@ def test_smooth_solve(shape, pe, prec, tol):
 
 @pytest.mark.parametrize("prec", ["fp32", "mixed"])
 @pytest.mark.parametrize("shape,pe,alpha", [((64, 64), 1, 50.0), ((240, 8, 6), 0, 0.5),
-                                            ((20, 70, 9), 1, 0.5), ((16, 20, 12), 0, 0.5)])
+                                            ((20, 70, 9), 1, 0.5), ((16, 20, 12), 0, 0.5),
+                                            # M + 1 = 64 P exactly (P = 1, 2, 4): the zero
+                                            # sample after the line lies past the staged data
+                                            ((63, 6, 5), 0, 0.5), ((127, 4, 3), 0, 0.5),
+                                            ((255, 3, 2), 0, 0.5)])
 def test_admm_one_iteration_from_the_same_state(shape, pe, alpha, prec):
     v = generate(1, shape, pe)
     P = O.make_problem(v.Ip, v.Im, v.h, alpha)
