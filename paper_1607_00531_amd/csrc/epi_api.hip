@@ -950,9 +950,9 @@ EPI_API epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts
     f.nb1 = sgs ? flat_blocks(n) : lb;
     launch_finalize(p->exec, f, p->st);
     for (int it = 0; it < opts->pcg_max; ++it) {
-      launch_matvec(p->exec, p->la, p->p, p->hd, p->ho, p->q, p->partial, p->st);
+      launch_matvec(p->exec, p->P, p->la, p->p, p->hd, p->ho, p->q, p->partial, p->st);
       f.kind = FIN_PCG_ALPHA;
-      f.nb1 = flat_blocks(n);
+      f.nb1 = lb;
       launch_finalize(p->exec, f, p->st);
       launch_pcg_update(p->exec, p->P, p->la, sgs ? EPI_PRECOND_NONE : opts->precond, p->hd,
                         p->ho, p->x, p->r, p->zz, p->p, p->q, p->partial, p->st);

@@ -11,6 +11,21 @@ namespace epi {
 
 int line_blocks(const LineArgs& a);
 
+// Launch a line kernel template for the faces-per-lane count P_ (1..8) as PP.
+#define EPI_DISPATCH_P(P_, CALL)                       \
+  switch (P_) {                                        \
+    case 1: { constexpr int PP = 1; CALL; } break;     \
+    case 2: { constexpr int PP = 2; CALL; } break;     \
+    case 3: { constexpr int PP = 3; CALL; } break;     \
+    case 4: { constexpr int PP = 4; CALL; } break;     \
+    case 5: { constexpr int PP = 5; CALL; } break;     \
+    case 6: { constexpr int PP = 6; CALL; } break;     \
+    case 7: { constexpr int PP = 7; CALL; } break;     \
+    case 8: { constexpr int PP = 8; CALL; } break;     \
+    default: break;                                    \
+  }
+
+
 // epi_line.hip
 void launch_eval(hipStream_t s, int P, int mode, LineArgs a, const float* b, const float* d,
                  int trial, int with_pen, float* grad, float* hdiag, float* hoff,
@@ -36,7 +51,7 @@ void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* 
 int flat_blocks(long long n);
 void launch_correct(hipStream_t s, int P, LineArgs a, const float* b, float* outp, float* outm,
                     double* partial);
-void launch_matvec(hipStream_t s, LineArgs a, const float* p, const float* hdiag,
+void launch_matvec(hipStream_t s, int P, LineArgs a, const float* p, const float* hdiag,
                    const float* hoff, float* q, double* partial, const DevState* st);
 void launch_pupdate(hipStream_t s, long long n, const float* z, float* p, const DevState* st);
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial);

@@ -43,29 +43,32 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
   }
   float b[P], nb[4][P];
   {
-    float tmp[P];
-    stage_in<P>(bsrc + (size_t)lc * NF, NF, valid, sbuf[wave][2], b, lane);
-    if (dsrc != nullptr) {
-      stage_in<P>(dsrc + (size_t)lc * NF, NF, valid, sbuf[wave][2], tmp, lane);
-#pragma unroll
-      for (int j = 0; j < P; ++j) b[j] = fmaf(lam, tmp[j], b[j]);
-    }
-    // transverse neighbours (j-1, j+1, k-1, k+1); missing ones get a copy of b
+    // the line and its transverse neighbours (j-1, j+1, k-1, k+1) in one memory round trip
+    // (a second one for the search direction d); a missing neighbour gets a copy of b
     const int nl[4] = {jj > 0 ? lc - 1 : -1, jj < a.m2 - 1 ? lc + 1 : -1,
                        kk > 0 ? lc - a.m2 : -1, kk < a.m3 - 1 ? lc + a.m2 : -1};
+    const float* srcs[5];
+    const int cnt[5] = {NF, NF, NF, NF, NF};
+    srcs[0] = bsrc + (size_t)lc * NF;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const bool ok = valid && nl[q] >= 0;
-      stage_in<P>(bsrc + (size_t)(ok ? nl[q] : 0) * NF, NF, ok, sbuf[wave][3 + q], nb[q], lane);
-      if (dsrc != nullptr) {
-        stage_in<P>(dsrc + (size_t)(ok ? nl[q] : 0) * NF, NF, ok, sbuf[wave][3 + q], tmp, lane);
+    for (int q = 0; q < 4; ++q) srcs[1 + q] = bsrc + (size_t)(nl[q] >= 0 ? nl[q] : lc) * NF;
+    float v[5][P];
+    stage_in_n<P, 5>(srcs, cnt, valid, &sbuf[wave][2][0], v, lane);
+    if (dsrc != nullptr) {
 #pragma unroll
-        for (int j = 0; j < P; ++j) nb[q][j] = fmaf(lam, tmp[j], nb[q][j]);
-      }
-      if (!ok) {
+      for (int q = 0; q < 5; ++q) srcs[q] = dsrc + (srcs[q] - bsrc);
+      float w[5][P];
+      stage_in_n<P, 5>(srcs, cnt, valid, &sbuf[wave][2][0], w, lane);
 #pragma unroll
-        for (int j = 0; j < P; ++j) nb[q][j] = b[j];
-      }
+      for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int j = 0; j < P; ++j) v[q][j] = fmaf(lam, w[q][j], v[q][j]);
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      b[j] = v[0][j];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nb[q][j] = (nl[q] >= 0) ? v[1 + q][j] : v[0][j];
     }
   }
 
@@ -190,36 +193,37 @@ __global__ __launch_bounds__(256) void k_pcg_init(LineArgs a, int precond,
                                                   float* __restrict__ x, float* __restrict__ r,
                                                   float* __restrict__ z, float* __restrict__ p,
                                                   double* partial) {
-  __shared__ float sbuf[EPI_LINE_WAVES][LineBuf<P>::SIZE];
+  __shared__ float sbuf[EPI_LINE_WAVES][4][LineBuf<P>::SIZE];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
   const int lc = valid ? line : 0;
   const int NF = a.M + 1;
   const size_t base = (size_t)lc * NF;
-  float rv[P], hd[P], ho[P], zv[P], zero[P];
-  stage_in<P>(grad + base, NF, valid, sbuf[wave], rv, lane);
-  stage_in<P>(hdiag + base, NF, valid, sbuf[wave], hd, lane);
-  stage_in<P>(hoff + base, NF, valid, sbuf[wave], ho, lane);
+  // all three lines in one memory round trip
+  const float* srcs[3] = {grad + base, hdiag + base, hoff + base};
+  const int cnt[3] = {NF, NF, NF};
+  float v[3][P];
+  stage_in_n<P, 3>(srcs, cnt, valid, &sbuf[wave][0][0], v, lane);
+  float o[4][P];   // x = 0, r = -grad, z = p = Pinv r
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    rv[j] = -rv[j];
-    zv[j] = rv[j];
-    zero[j] = 0.0f;
+    o[0][j] = 0.0f;
+    o[1][j] = -v[0][j];
+    o[2][j] = o[1][j];
   }
-  precond_apply<P>(a, precond, hd, ho, cross_diag(a, lc % a.m2, lc / a.m2), zv, lane);
+  precond_apply<P>(a, precond, v[1], v[2], cross_diag(a, lc % a.m2, lc / a.m2), o[2], lane);
   double acc[NQ_PCG] = {0, 0};
 #pragma unroll
   for (int j = 0; j < P; ++j) {
+    o[3][j] = o[2][j];
     if (valid && P * lane + j < NF) {
-      acc[0] += (double)rv[j] * zv[j];
-      acc[1] += (double)rv[j] * rv[j];
+      acc[0] += (double)o[1][j] * o[2][j];
+      acc[1] += (double)o[1][j] * o[1][j];
     }
   }
-  stage_out<P>(x + base, NF, valid, sbuf[wave], zero, lane);
-  stage_out<P>(r + base, NF, valid, sbuf[wave], rv, lane);
-  stage_out<P>(z + base, NF, valid, sbuf[wave], zv, lane);
-  stage_out<P>(p + base, NF, valid, sbuf[wave], zv, lane);
+  float* dst[4] = {x + base, r + base, z + base, p + base};
+  stage_out_n<P, 4>(dst, NF, valid, &sbuf[wave][0][0], o, lane);
   block_partials<NQ_PCG>(acc, partial, blockIdx.x);
 }
 
@@ -234,7 +238,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(LineArgs a, int precond,
                                                     const float* __restrict__ q, double* partial,
                                                     const DevState* st) {
   if (st->pcg_done) return;
-  __shared__ float sbuf[EPI_LINE_WAVES][LineBuf<P>::SIZE];
+  __shared__ float sbuf[EPI_LINE_WAVES][6][LineBuf<P>::SIZE];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
@@ -242,32 +246,29 @@ __global__ __launch_bounds__(256) void k_pcg_update(LineArgs a, int precond,
   const int NF = a.M + 1;
   const size_t base = (size_t)lc * NF;
   const float al = (float)st->alpha_cg;
-  float xv[P], rv[P], pv[P], qv[P], hd[P], ho[P];
-  stage_in<P>(x + base, NF, valid, sbuf[wave], xv, lane);
-  stage_in<P>(r + base, NF, valid, sbuf[wave], rv, lane);
-  stage_in<P>(p + base, NF, valid, sbuf[wave], pv, lane);
-  stage_in<P>(q + base, NF, valid, sbuf[wave], qv, lane);
-  stage_in<P>(hdiag + base, NF, valid, sbuf[wave], hd, lane);
-  stage_in<P>(hoff + base, NF, valid, sbuf[wave], ho, lane);
-  float zv[P];
+  // all six lines in one memory round trip: x, r, p, q, Hessian diagonal and off-diagonal
+  const float* srcs[6] = {x + base, r + base, p + base, q + base, hdiag + base, hoff + base};
+  const int cnt[6] = {NF, NF, NF, NF, NF, NF};
+  float v[6][P];
+  stage_in_n<P, 6>(srcs, cnt, valid, &sbuf[wave][0][0], v, lane);
+  float o[3][P];   // x, r, z
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    xv[j] = fmaf(al, pv[j], xv[j]);
-    rv[j] = fmaf(-al, qv[j], rv[j]);
-    zv[j] = rv[j];
+    o[0][j] = fmaf(al, v[2][j], v[0][j]);
+    o[1][j] = fmaf(-al, v[3][j], v[1][j]);
+    o[2][j] = o[1][j];
   }
-  precond_apply<P>(a, precond, hd, ho, cross_diag(a, lc % a.m2, lc / a.m2), zv, lane);
+  precond_apply<P>(a, precond, v[4], v[5], cross_diag(a, lc % a.m2, lc / a.m2), o[2], lane);
   double acc[NQ_PCG] = {0, 0};
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     if (valid && P * lane + j < NF) {
-      acc[0] += (double)rv[j] * rv[j];
-      acc[1] += (double)rv[j] * zv[j];
+      acc[0] += (double)o[1][j] * o[1][j];
+      acc[1] += (double)o[1][j] * o[2][j];
     }
   }
-  stage_out<P>(x + base, NF, valid, sbuf[wave], xv, lane);
-  stage_out<P>(r + base, NF, valid, sbuf[wave], rv, lane);
-  stage_out<P>(z + base, NF, valid, sbuf[wave], zv, lane);
+  float* dst[3] = {x + base, r + base, z + base};
+  stage_out_n<P, 3>(dst, NF, valid, &sbuf[wave][0][0], o, lane);
   block_partials<NQ_PCG>(acc, partial, blockIdx.x);
 }
 
@@ -483,19 +484,6 @@ __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __res
 // ------------------------------------------------------------------------------------
 // Host-side launchers
 // ------------------------------------------------------------------------------------
-#define EPI_DISPATCH_P(P_, CALL)                       \
-  switch (P_) {                                        \
-    case 1: { constexpr int PP = 1; CALL; } break;     \
-    case 2: { constexpr int PP = 2; CALL; } break;     \
-    case 3: { constexpr int PP = 3; CALL; } break;     \
-    case 4: { constexpr int PP = 4; CALL; } break;     \
-    case 5: { constexpr int PP = 5; CALL; } break;     \
-    case 6: { constexpr int PP = 6; CALL; } break;     \
-    case 7: { constexpr int PP = 7; CALL; } break;     \
-    case 8: { constexpr int PP = 8; CALL; } break;     \
-    default: break;                                    \
-  }
-
 int line_blocks(const LineArgs& a) { return (a.L + EPI_LINE_WAVES - 1) / EPI_LINE_WAVES; }
 
 void launch_eval(hipStream_t s, int P, int mode, LineArgs a, const float* b, const float* d,

@@ -24,36 +24,47 @@ __device__ __forceinline__ void chunk_of(long long n, long long& lo, long long& 
 }
 
 // q = H_JGN p = (line tridiagonal) p + alpha v (D2'D2 + D3'D3) p  (eq. dJGN, Section 3:
-// the transverse coupling of the regulariser is a Neumann Laplacian stencil); partial p.q
+// the transverse coupling of the regulariser is a Neumann Laplacian stencil); partial p.q.
+// One wavefront per PE line (lane-contiguous faces, 32-bit index arithmetic, no division
+// per element); the neighbours along the line come from the same cache lines, those of
+// the neighbouring lines (j +- 1, k +- 1) from L2.
+template <int P>
 __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restrict__ p,
                                                 const float* __restrict__ hd,
                                                 const float* __restrict__ ho,
                                                 float* __restrict__ q, double* partial,
                                                 const DevState* st) {
   if (st->pcg_done) return;
-  const int NF = a.M + 1;
-  const long long n = (long long)NF * a.L;
-  const long long plane = (long long)NF * a.m2;
-  long long lo, hi;
-  chunk_of(n, lo, hi);
-  const float av = a.alpha * a.v;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int blk = xcd_remap(blockIdx.x, a.nblk);
+  const int line = blk * EPI_LINE_WAVES + wave;
   double acc[1] = {0.0};
-  for (long long f = lo + threadIdx.x; f < hi; f += blockDim.x) {
-    const int i = (int)(f % NF);
-    const long long line = f / NF;
-    const int jj = (int)(line % a.m2), kk = (int)(line / a.m2);
-    const float pc = p[f];
-    float y = hd[f] * pc;
-    if (i > 0) y = fmaf(ho[f - 1], p[f - 1], y);
-    if (i < NF - 1) y = fmaf(ho[f], p[f + 1], y);
-    float l2 = 0.0f, l3 = 0.0f;
-    if (jj > 0) l2 += pc - p[f - NF];
-    if (jj < a.m2 - 1) l2 += pc - p[f + NF];
-    if (kk > 0) l3 += pc - p[f - plane];
-    if (kk < a.m3 - 1) l3 += pc - p[f + plane];
-    y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
-    q[f] = y;
-    acc[0] += (double)pc * y;
+  if (line < a.L) {
+    const int NF = a.M + 1;
+    const int jj = line % a.m2, kk = line / a.m2;
+    const size_t base = (size_t)line * NF;
+    const int plane = NF * a.m2;
+    const float* pl = p + base;
+    const float av = a.alpha * a.v;
+    const bool j0 = jj > 0, j1 = jj < a.m2 - 1, k0 = kk > 0, k1 = kk < a.m3 - 1;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int i = lane + 64 * j;
+      if (j < P - 1 || i < NF) {
+        const float pc = pl[i];
+        float y = hd[base + i] * pc;
+        if (i > 0) y = fmaf(ho[base + i - 1], pl[i - 1], y);
+        if (i < NF - 1) y = fmaf(ho[base + i], pl[i + 1], y);
+        float l2 = 0.0f, l3 = 0.0f;
+        if (j0) l2 += pc - pl[i - NF];
+        if (j1) l2 += pc - pl[i + NF];
+        if (k0) l3 += pc - pl[i - plane];
+        if (k1) l3 += pc - pl[i + plane];
+        y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
+        store_stream(&q[base + i], y);
+        acc[0] += (double)pc * y;
+      }
+    }
   }
   block_partials<1>(acc, partial, blockIdx.x);
 }
@@ -266,11 +277,12 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f, DevState* st) {
 // ------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------
-void launch_matvec(hipStream_t s, LineArgs a, const float* p, const float* hdiag,
+void launch_matvec(hipStream_t s, int P, LineArgs a, const float* p, const float* hdiag,
                    const float* hoff, float* q, double* partial, const DevState* st) {
-  const long long n = (long long)(a.M + 1) * a.L;
-  hipLaunchKernelGGL(k_matvec, dim3(flat_blocks(n)), dim3(256), 0, s, a, p, hdiag, hoff, q,
-                     partial, st);
+  const int nb = line_blocks(a);
+  a.nblk = nb;
+  EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_matvec<PP>), dim3(nb), dim3(256), 0, s, a, p, hdiag,
+                                       hoff, q, partial, st));
 }
 void launch_pupdate(hipStream_t s, long long n, const float* z, float* p, const DevState* st) {
   hipLaunchKernelGGL(k_pupdate, dim3(flat_blocks(n)), dim3(256), 0, s, n, z, p, st);
