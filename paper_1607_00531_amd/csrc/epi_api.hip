@@ -949,13 +949,22 @@ EPI_API epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts
     f.kind = FIN_PCG_INIT;
     f.nb1 = sgs ? flat_blocks(n) : lb;
     launch_finalize(p->exec, f, p->st);
+    // the direction p alternates between two buffers: from the second PCG iteration on, the
+    // matvec forms p = z + beta p_old itself and writes it to the other buffer
+    float* pbuf[2] = {p->p, p->t1};
     for (int it = 0; it < opts->pcg_max; ++it) {
-      launch_matvec(p->exec, p->P, p->la, p->p, p->hd, p->ho, p->q, p->partial, p->st);
+      float* pcur = pbuf[it & 1];
+      if (it == 0)
+        launch_matvec(p->exec, p->P, p->la, nullptr, pcur, nullptr, p->hd, p->ho, p->q,
+                      p->partial, p->st);
+      else
+        launch_matvec(p->exec, p->P, p->la, p->zz, pbuf[(it - 1) & 1], pcur, p->hd, p->ho,
+                      p->q, p->partial, p->st);
       f.kind = FIN_PCG_ALPHA;
       f.nb1 = lb;
       launch_finalize(p->exec, f, p->st);
       launch_pcg_update(p->exec, p->P, p->la, sgs ? EPI_PRECOND_NONE : opts->precond, p->hd,
-                        p->ho, p->x, p->r, p->zz, p->p, p->q, p->partial, p->st);
+                        p->ho, p->x, p->r, p->zz, pcur, p->q, p->partial, p->st);
       if (sgs) {
         launch_sgs(p->exec, p->P, p->la, p->hd, p->ho, p->r, p->zz, p->st, 1);
         launch_sgs_finish(p->exec, n, p->r, p->zz, nullptr, p->partial, 0, p->st);
@@ -963,7 +972,6 @@ EPI_API epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts
       f.kind = FIN_PCG_UPDATE;
       f.nb1 = sgs ? flat_blocks(n) : lb;
       launch_finalize(p->exec, f, p->st);
-      launch_pupdate(p->exec, n, p->zz, p->p, p->st);
       CHKLAUNCH();
       if ((it & 3) == 3 && it + 1 < opts->pcg_max) {
         HIPCHK(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));

@@ -51,9 +51,10 @@ void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* 
 int flat_blocks(long long n);
 void launch_correct(hipStream_t s, int P, LineArgs a, const float* b, float* outp, float* outm,
                     double* partial);
-void launch_matvec(hipStream_t s, int P, LineArgs a, const float* p, const float* hdiag,
-                   const float* hoff, float* q, double* partial, const DevState* st);
-void launch_pupdate(hipStream_t s, long long n, const float* z, float* p, const DevState* st);
+// q = H_JGN p with p = pold (z null) or p = z + beta pold written to pnew (fused update)
+void launch_matvec(hipStream_t s, int P, LineArgs a, const float* z, const float* pold,
+                   float* pnew, const float* hdiag, const float* hoff, float* q, double* partial,
+                   const DevState* st);
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial);
 void launch_sgs_finish(hipStream_t s, long long n, const float* r, const float* z, float* p,
                        double* partial, int first, const DevState* st);

@@ -25,11 +25,16 @@ __device__ __forceinline__ void chunk_of(long long n, long long& lo, long long& 
 
 // q = H_JGN p = (line tridiagonal) p + alpha v (D2'D2 + D3'D3) p  (eq. dJGN, Section 3:
 // the transverse coupling of the regulariser is a Neumann Laplacian stencil); partial p.q.
-// One wavefront per PE line (lane-contiguous faces, 32-bit index arithmetic, no division
-// per element); the neighbours along the line come from the same cache lines, those of
-// the neighbouring lines (j +- 1, k +- 1) from L2.
-template <int P>
-__global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restrict__ p,
+// One wavefront per PE line (lane-contiguous faces, 32-bit index arithmetic); the
+// neighbours along the line come from the same cache lines, those of the neighbouring
+// lines (j +- 1, k +- 1) from L2.
+// DIR: the PCG direction update is fused in: p = z + beta p_old is formed on the fly at
+// every stencil point (the same value the separate update computes), written to pnew, and
+// q = H p; otherwise p = pold.
+template <int P, bool DIR>
+__global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restrict__ z,
+                                                const float* __restrict__ pold,
+                                                float* __restrict__ pnew,
                                                 const float* __restrict__ hd,
                                                 const float* __restrict__ ho,
                                                 float* __restrict__ q, double* partial,
@@ -38,45 +43,39 @@ __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restr
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = xcd_remap(blockIdx.x, a.nblk);
   const int line = blk * EPI_LINE_WAVES + wave;
+  const float be = DIR ? (float)st->beta_cg : 0.0f;
   double acc[1] = {0.0};
   if (line < a.L) {
     const int NF = a.M + 1;
     const int jj = line % a.m2, kk = line / a.m2;
     const size_t base = (size_t)line * NF;
     const int plane = NF * a.m2;
-    const float* pl = p + base;
+    const float* pl = pold + base;
+    const float* zl = DIR ? z + base : nullptr;
+    const auto pat = [&](int o) { return DIR ? fmaf(be, pl[o], zl[o]) : pl[o]; };
     const float av = a.alpha * a.v;
     const bool j0 = jj > 0, j1 = jj < a.m2 - 1, k0 = kk > 0, k1 = kk < a.m3 - 1;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const int i = lane + 64 * j;
       if (j < P - 1 || i < NF) {
-        const float pc = pl[i];
+        const float pc = pat(i);
         float y = hd[base + i] * pc;
-        if (i > 0) y = fmaf(ho[base + i - 1], pl[i - 1], y);
-        if (i < NF - 1) y = fmaf(ho[base + i], pl[i + 1], y);
+        if (i > 0) y = fmaf(ho[base + i - 1], pat(i - 1), y);
+        if (i < NF - 1) y = fmaf(ho[base + i], pat(i + 1), y);
         float l2 = 0.0f, l3 = 0.0f;
-        if (j0) l2 += pc - pl[i - NF];
-        if (j1) l2 += pc - pl[i + NF];
-        if (k0) l3 += pc - pl[i - plane];
-        if (k1) l3 += pc - pl[i + plane];
+        if (j0) l2 += pc - pat(i - NF);
+        if (j1) l2 += pc - pat(i + NF);
+        if (k0) l3 += pc - pat(i - plane);
+        if (k1) l3 += pc - pat(i + plane);
         y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
+        if (DIR) store_stream(&pnew[base + i], pc);
         store_stream(&q[base + i], y);
         acc[0] += (double)pc * y;
       }
     }
   }
   block_partials<1>(acc, partial, blockIdx.x);
-}
-
-// p = z + beta p (PCG direction update)
-__global__ __launch_bounds__(256) void k_pupdate(long long n, const float* __restrict__ z,
-                                                 float* __restrict__ p, const DevState* st) {
-  if (st->pcg_done) return;
-  const float be = (float)st->beta_cg;
-  long long lo, hi;
-  chunk_of(n, lo, hi);
-  for (long long f = lo + threadIdx.x; f < hi; f += blockDim.x) p[f] = fmaf(be, p[f], z[f]);
 }
 
 __global__ __launch_bounds__(256) void k_dot(long long n, const float* __restrict__ x,
@@ -277,15 +276,18 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f, DevState* st) {
 // ------------------------------------------------------------------------------------
 // Launchers
 // ------------------------------------------------------------------------------------
-void launch_matvec(hipStream_t s, int P, LineArgs a, const float* p, const float* hdiag,
-                   const float* hoff, float* q, double* partial, const DevState* st) {
+void launch_matvec(hipStream_t s, int P, LineArgs a, const float* z, const float* pold,
+                   float* pnew, const float* hdiag, const float* hoff, float* q, double* partial,
+                   const DevState* st) {
   const int nb = line_blocks(a);
   a.nblk = nb;
-  EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_matvec<PP>), dim3(nb), dim3(256), 0, s, a, p, hdiag,
-                                       hoff, q, partial, st));
-}
-void launch_pupdate(hipStream_t s, long long n, const float* z, float* p, const DevState* st) {
-  hipLaunchKernelGGL(k_pupdate, dim3(flat_blocks(n)), dim3(256), 0, s, n, z, p, st);
+  if (z != nullptr) {
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_matvec<PP, true>), dim3(nb), dim3(256), 0, s, a, z,
+                                         pold, pnew, hdiag, hoff, q, partial, st));
+  } else {
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_matvec<PP, false>), dim3(nb), dim3(256), 0, s, a,
+                                         nullptr, pold, nullptr, hdiag, hoff, q, partial, st));
+  }
 }
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial) {
   hipLaunchKernelGGL(k_dot, dim3(flat_blocks(n)), dim3(256), 0, s, n, x, y, partial);
