@@ -15,6 +15,22 @@ namespace epi {
 // ------------------------------------------------------------------------------------
 // Shuffles and reductions within one wavefront
 // ------------------------------------------------------------------------------------
+// Neighbour exchange by one lane across the whole wavefront as a DPP move (wave_shr:1 /
+// wave_shl:1 of the GFX9 family: a VALU operation, no LDS round trip); the lane without a
+// neighbour receives 0. All 64 lanes must be active.
+__device__ __forceinline__ float dpp_prev_lane(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float dpp_next_lane(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x130, 0xf, 0xf, true));
+}
+// value of v in lane l (wave-uniform)
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
 __device__ __forceinline__ float shfl_up0(float v, int d, int lane) {
   float t = __shfl_up(v, d, EPI_WAVE);
   return lane >= d ? t : 0.0f;

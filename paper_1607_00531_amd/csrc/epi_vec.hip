@@ -45,34 +45,58 @@ __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restr
   const int line = blk * EPI_LINE_WAVES + wave;
   const float be = DIR ? (float)st->beta_cg : 0.0f;
   double acc[1] = {0.0};
-  if (line < a.L) {
-    const int NF = a.M + 1;
-    const int jj = line % a.m2, kk = line / a.m2;
-    const size_t base = (size_t)line * NF;
-    const int plane = NF * a.m2;
-    const float* pl = pold + base;
-    const float* zl = DIR ? z + base : nullptr;
-    const auto pat = [&](int o) { return DIR ? fmaf(be, pl[o], zl[o]) : pl[o]; };
-    const float av = a.alpha * a.v;
-    const bool j0 = jj > 0, j1 = jj < a.m2 - 1, k0 = kk > 0, k1 = kk < a.m3 - 1;
+  // the whole wavefront stays active (the neighbour exchanges along the line are lane
+  // shifts); invalid lines and faces work on zeros and store nothing
+  const bool lv = line < a.L;
+  const int lc = lv ? line : 0;
+  const int NF = a.M + 1;
+  const int jj = lc % a.m2, kk = lc / a.m2;
+  const size_t base = (size_t)lc * NF;
+  const int plane = NF * a.m2;
+  const float* pl = pold + base;
+  const float* zl = DIR ? z + base : nullptr;
+  const auto pat = [&](int o) { return DIR ? fmaf(be, pl[o], zl[o]) : pl[o]; };
+  const float av = a.alpha * a.v;
+  const bool j0 = jj > 0, j1 = jj < a.m2 - 1, k0 = kk > 0, k1 = kk < a.m3 - 1;
+  float pc[P], hdv[P], hov[P];
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int i = lane + 64 * j;
-      if (j < P - 1 || i < NF) {
-        const float pc = pat(i);
-        float y = hd[base + i] * pc;
-        if (i > 0) y = fmaf(ho[base + i - 1], pat(i - 1), y);
-        if (i < NF - 1) y = fmaf(ho[base + i], pat(i + 1), y);
-        float l2 = 0.0f, l3 = 0.0f;
-        if (j0) l2 += pc - pat(i - NF);
-        if (j1) l2 += pc - pat(i + NF);
-        if (k0) l3 += pc - pat(i - plane);
-        if (k1) l3 += pc - pat(i + plane);
-        y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
-        if (DIR) store_stream(&pnew[base + i], pc);
-        store_stream(&q[base + i], y);
-        acc[0] += (double)pc * y;
+  for (int j = 0; j < P; ++j) {
+    const int i = lane + 64 * j;
+    const bool ok = lv && (j < P - 1 || i < NF);
+    pc[j] = ok ? pat(i) : 0.0f;
+    hdv[j] = ok ? hd[base + i] : 0.0f;
+    hov[j] = ok ? ho[base + i] : 0.0f;
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int i = lane + 64 * j;
+    // faces i - 1 and i + 1 (lane shifts; across a 64-face block from the end lane)
+    float pp = dpp_prev_lane(pc[j]), ho_p = dpp_prev_lane(hov[j]), pn = dpp_next_lane(pc[j]);
+    if (j > 0) {
+      const float e0 = read_lane(pc[j - 1], 63), e1 = read_lane(hov[j - 1], 63);
+      if (lane == 0) {
+        pp = e0;
+        ho_p = e1;
       }
+    }
+    if (j < P - 1) {
+      const float e2 = read_lane(pc[j + 1], 0);
+      if (lane == 63) pn = e2;
+    }
+    const bool ok = lv && (j < P - 1 || i < NF);
+    if (ok) {
+      float y = hdv[j] * pc[j];
+      if (i > 0) y = fmaf(ho_p, pp, y);
+      if (i < NF - 1) y = fmaf(hov[j], pn, y);
+      float l2 = 0.0f, l3 = 0.0f;
+      if (j0) l2 += pc[j] - pat(i - NF);
+      if (j1) l2 += pc[j] - pat(i + NF);
+      if (k0) l3 += pc[j] - pat(i - plane);
+      if (k1) l3 += pc[j] - pat(i + plane);
+      y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
+      if (DIR) store_stream(&pnew[base + i], pc[j]);
+      store_stream(&q[base + i], y);
+      acc[0] += (double)pc[j] * y;
     }
   }
   block_partials<1>(acc, partial, blockIdx.x);
