@@ -53,6 +53,26 @@ __device__ __forceinline__ void st_stream_at(float* base, unsigned boff, float v
   store_stream(reinterpret_cast<float*>(reinterpret_cast<char*>(base) + boff), v);
 }
 
+// LDS of one workgroup: the input tile (reused for the float32 output tile) and, for the
+// split-bfloat16 kernels, the spectral scale of every row tile row (RT * 16 floats).
+__host__ __device__ inline size_t dct_tile_bytes(int prec, const GemmArgs& g) {
+  const size_t out_tile = (size_t)g.RT * 16 * (DCT_NT + 4) * sizeof(float);
+  size_t in_tile;
+  if (prec == 1) {
+    // hi and lo tiles, both halves of the even/odd split (KS steps of 32 each) + padding
+    in_tile = (size_t)2 * DCT_NT * (2 * g.KS * 32 + EPI_DCT_KPAD) * sizeof(unsigned short);
+  } else {
+    // the fused pass writes back all 16-row tiles, which may exceed the padded contraction
+    const int rows = g.KS * 4 > g.RT * 16 ? g.KS * 4 : g.RT * 16;
+    in_tile = (size_t)rows * (DCT_NT + 4) * sizeof(float);
+  }
+  const size_t t = in_tile > out_tile ? in_tile : out_tile;
+  return (t + 15) & ~(size_t)15;
+}
+__host__ __device__ inline size_t dct_lds_bytes(int prec, const GemmArgs& g) {
+  return dct_tile_bytes(prec, g) + (prec == 1 ? (size_t)g.RT * 16 * sizeof(float) : 0);
+}
+
 // Tile index -> (batch, first column), walking each XCD over a contiguous range.
 __device__ __forceinline__ int dct_tile(const GemmArgs& g, int& batch, int& c0) {
   const int ntile = g.nbatch * g.col_tiles;
@@ -276,6 +296,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
   constexpr int SLOTS = (2 * KSM + HW - 1) / HW;   // row tiles per wavefront (RTh <= 2 KSM)
   constexpr int NG = 4 * KSM;                      // 8-row groups per half (maximum)
   constexpr int NIT = (NG + NW - 1) / NW;
+  static_assert(64 * KSM <= 64 * NW, "one thread per scale-table row");
   const int N = g.rows, ce = (N + 1) / 2, fo = N / 2;
   const int KPh = g.KS * 32;                       // contraction extent of one half
   const int KP = 2 * KPh + EPI_DCT_KPAD;
@@ -283,6 +304,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
   const bool fwd_in = FUSED || g.dir == 0;
   unsigned short* Lhi = lds_bf;
   unsigned short* Llo = lds_bf + DCT_NT * KP;
+  float* SC = reinterpret_cast<float*>(reinterpret_cast<char*>(lds_bf) + dct_tile_bytes(1, g));
   const size_t bofs = (size_t)batch * g.bstride;
   const float* in = g.in + bofs + c0;
   const int lane = threadIdx.x & 63;
@@ -309,6 +331,19 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
         const bool okb = live && q < fo;
         va[it][e] = oka ? ld_at<float>(in + (size_t)ra * g.ld, lane4) : 0.0f;
         vb[it][e] = okb ? ld_at<float>(in + (size_t)(okb ? rb : 0) * g.ld, lane4) : 0.0f;
+      }
+    }
+    if (FUSED) {
+      // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)) of each row tile row
+      // in half order (0 beyond the half's length), read after the first product
+      const int hr = RTh * 16, rows = 2 * hr;
+      if ((int)threadIdx.x < rows) {
+        const int h = (int)threadIdx.x >= hr, row = (int)threadIdx.x - h * hr;
+        const float rho = (float)g.st->rho;
+        const float lb = (g.lam_batch != nullptr) ? g.lam_batch[batch] : 0.0f;
+        float sc = 0.0f;
+        if (row < (h ? fo : ce)) sc = rho * rcp_f(rho + g.alpha * (g.lam_row[h * ce + row] + lb));
+        SC[threadIdx.x] = sc;
       }
     }
 #pragma unroll
@@ -361,9 +396,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
   if (FUSED) {
     // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)) in half order, then
     // the inverse from the same LDS blocks
-    const float rho = (float)g.st->rho;
-    const float lb = (g.lam_batch != nullptr) ? g.lam_batch[batch] : 0.0f;
-    const int cnt = half ? fo : ce;
+    const float* sch = SC + half * RTh * 16;
     __syncthreads();   // all waves finished reading the input tile
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -371,11 +404,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
         const int r0 = (lw + HW * s) * 16 + (lane >> 4) * 4;   // row within the half
         float sc[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = r0 + r;
-          sc[r] = (row < cnt) ? rho * rcp_f(rho + g.alpha * (g.lam_row[half * ce + row] + lb))
-                              : 0.0f;
-        }
+        for (int r = 0; r < 4; ++r) sc[r] = sch[r0 + r];
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
           const int col = ct * 16 + (lane & 15);
@@ -492,19 +521,6 @@ __device__ __forceinline__ void dct_f32_body(const GemmArgs& g, int batch, int c
 }
 
 // dynamic LDS bytes of one tile
-__host__ __device__ inline size_t dct_lds_bytes(int prec, const GemmArgs& g) {
-  const size_t out_tile = (size_t)g.RT * 16 * (DCT_NT + 4) * sizeof(float);
-  size_t in_tile;
-  if (prec == 1) {
-    // hi and lo tiles, both halves of the even/odd split (KS steps of 32 each) + padding
-    in_tile = (size_t)2 * DCT_NT * (2 * g.KS * 32 + EPI_DCT_KPAD) * sizeof(unsigned short);
-  } else {
-    // the fused pass writes back all 16-row tiles, which may exceed the padded contraction
-    const int rows = g.KS * 4 > g.RT * 16 ? g.KS * 4 : g.RT * 16;
-    in_tile = (size_t)rows * (DCT_NT + 4) * sizeof(float);
-  }
-  return in_tile > out_tile ? in_tile : out_tile;
-}
 
 // ------------------------------------------------------------------------------------
 }  // namespace epi
