@@ -79,6 +79,10 @@ struct epi_problem {
   int hard_blocks = 0;
   // DCT tables (packed MFMA fragments), eigenvalues
   DctTables tab;
+  // per-slice j-axis operators for one fixed rho (split-bfloat16; zop_rho 0: not built)
+  unsigned short* zop = nullptr;
+  double zop_rho = 0.0;
+  bool use_zop = false;
   double* hist = nullptr;
   int hist_cap = 0;
   // captured ADMM chunk
@@ -86,6 +90,7 @@ struct epi_problem {
   hipGraph_t graph = nullptr;
   int g_chunk = 0, g_sqp = 0;
   float *g_b = nullptr, *g_z = nullptr, *g_u = nullptr;
+  bool g_zop = false;
   // per-kernel event timing (epi_profile_admm)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
@@ -334,7 +339,7 @@ EPI_API void epi_destroy(epi_problem* p) {
   if (p->exec) (void)hipStreamSynchronize(p->exec);
   free_graph(p);
   void* bufs[] = {p->w, p->t1, p->t2, p->g, p->hd, p->ho, p->x, p->r, p->zz, p->p, p->q,
-                  p->partial, p->partial_e, p->st, p->hard_list, p->hist};
+                  p->partial, p->partial_e, p->st, p->hard_list, p->hist, p->zop};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_dct_tables(&p->tab);
@@ -592,7 +597,41 @@ static GemmArgs gemm_axis3(const epi_problem* p, const float* in, float* out, bo
   return make_gemm_axis3(p->M, p->m2, p->m3, (float)p->grid.alpha, p->tab, in, out, inverse, p->st);
 }
 static GemmArgs gemm_axis2(const epi_problem* p, const float* in, float* out) {
-  return make_gemm_axis2(p->M, p->m2, p->m3, (float)p->grid.alpha, p->tab, in, out, p->st);
+  GemmArgs g = make_gemm_axis2(p->M, p->m2, p->m3, (float)p->grid.alpha, p->tab, in, out, p->st);
+  if (p->use_zop) {
+    g.dir = 2;
+    g.A1 = p->zop;
+    g.A2 = nullptr;
+    g.a_bstride = 2LL * p->tab.RT2 * p->tab.KS2 * 64;
+  }
+  return g;
+}
+static void launch_axis2(const epi_problem* p, int prec, const GemmArgs& g) {
+  if (p->use_zop) launch_dct_axis2_op(p->exec, prec, g);
+  else launch_dct_axis2_fused(p->exec, prec, g);
+}
+
+// With a fixed rho the split-bfloat16 z-step takes the j-axis forward, spectral scale and
+// inverse of each k-slice as one product with the slice's operator C_h^T S_h C_h (built
+// once per rho); with an adaptive rho, or in float32, the fused pass applies the three.
+static epi_status prepare_zop(epi_problem* p, double rho, bool fixed_rho) {
+  p->use_zop = false;
+  if (p->grid.precision != EPI_PREC_MIXED || !fixed_rho || (p->m2 + 1) / 2 > 128) return EPI_OK;
+  if (!p->zop) {
+    const size_t bytes = zop_bytes(p->m2, p->m3, p->tab.RT2, p->tab.KS2);
+    HIPCHK(hipMalloc(&p->zop, bytes));
+    HIPCHK(hipMemsetAsync(p->zop, 0, bytes, p->exec));
+    p->zop_rho = 0.0;
+  }
+  if (p->zop_rho != rho) {
+    if (launch_build_zop(p->exec, p->m2, p->m3, p->grid.h[1], p->grid.h[2], p->grid.alpha, rho,
+                         p->tab.RT2, p->tab.KS2, p->zop))
+      return fail(EPI_EINVAL, "transform length %d not supported", p->m2);
+    CHKLAUNCH();
+    p->zop_rho = rho;
+  }
+  p->use_zop = true;
+  return EPI_OK;
 }
 
 // z = smoothness solve of w; with admm != 0 the last pass performs the u-step epilogue
@@ -612,7 +651,7 @@ static epi_status launch_zstep(epi_problem* p, const float* w, float* z, int adm
       g2.partial = p->partial_e;
     }
     prof_begin(p, EPI_K_DCT_LAST);
-    launch_dct_axis2_fused(p->exec, prec, g2);
+    launch_axis2(p, prec, g2);
     prof_end(p);
     CHKLAUNCH();
     return EPI_OK;
@@ -626,7 +665,7 @@ static epi_status launch_zstep(epi_problem* p, const float* w, float* z, int adm
   GemmArgs g2 = gemm_axis2(p, p->t1, p->t2);
   g2.done = done;
   prof_begin(p, EPI_K_DCT_AXIS2);
-  launch_dct_axis2_fused(p->exec, prec, g2);
+  launch_axis2(p, prec, g2);
   prof_end(p);
   CHKLAUNCH();
   GemmArgs g3 = gemm_axis3(p, p->t2, z, true);
@@ -656,7 +695,9 @@ EPI_API epi_status epi_smooth_solve(epi_problem* p, const float* d_w, double rho
   HIPCHK(hipStreamSynchronize(p->exec));   // the pinned mirror is reused below
   p->st_h->rho = rho;
   HIPCHK(hipMemcpyAsync(&p->st->rho, &p->st_h->rho, sizeof(double), hipMemcpyHostToDevice, p->exec));
-  epi_status s = launch_zstep(p, d_w, d_z, 0, nullptr, nullptr);
+  epi_status s = prepare_zop(p, rho, true);
+  if (s != EPI_OK) return s;
+  s = launch_zstep(p, d_w, d_z, 0, nullptr, nullptr);
   if (s != EPI_OK) return s;
   HIPCHK(hipStreamSynchronize(p->exec));
   leave(p);
@@ -759,11 +800,13 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
   h->admm_done = opts->max_iter == 0 ? 2 : 0;
   init_rho_state(h, opts);
   HIPCHK(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->exec));
+  s = prepare_zop(p, opts->rho, opts->rho_mode == EPI_RHO_FIXED);
+  if (s != EPI_OK) return s;
 
   const int chunk = opts->check_every;
   const bool use_graph = !p->prof_on;
   if (use_graph && (p->g_chunk != chunk || p->g_sqp != opts->sqp_iters || p->g_b != d_b ||
-                    p->g_z != d_z || p->g_u != d_u)) {
+                    p->g_z != d_z || p->g_u != d_u || p->g_zop != p->use_zop)) {
     free_graph(p);
     HIPCHK(hipStreamBeginCapture(p->exec, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < chunk; ++i) {
@@ -782,6 +825,7 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
     p->g_b = d_b;
     p->g_z = d_z;
     p->g_u = d_u;
+    p->g_zop = p->use_zop;
   }
   int done = opts->max_iter == 0;
   int launched = 0;

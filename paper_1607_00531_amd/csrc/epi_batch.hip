@@ -187,6 +187,7 @@ struct SlotHost {
   double* hist = nullptr;
   int hist_len = 0;
   DctTables tab;
+  unsigned short* zop = nullptr;   // per-slice j-axis operators (split-bfloat16, fixed rho)
   int64_t footprint = 0;
   epi_admm_opts opts{};
 };
@@ -197,7 +198,10 @@ int64_t workspace_bytes(const epi_grid* g, int max_iter) {
   const long long tiles = std::max<long long>(tiles_axis3((int)M, (int)m2), tiles_axis2((int)M, (int)m3));
   const long long part = std::max<long long>(tiles * NQ_ADMM_E, 4096);
   const long long tables = 4 * (m2 * m2 + m3 * m3) * 4 + 4 * (m2 + m3);
-  return 3 * n * 4 + part * 8 + 4LL * std::max(max_iter, 1) * 8 + tables;
+  // the split-bfloat16 per-slice operators of a fixed-rho volume (counted for every volume)
+  const long long ce = (m2 + 1) / 2;
+  const long long zop = (long long)zop_bytes((int)m2, (int)m3, 2 * (int)((ce + 15) / 16), (int)((ce + 31) / 32));
+  return 3 * n * 4 + part * 8 + 4LL * std::max(max_iter, 1) * 8 + tables + zop;
 }
 
 }  // namespace
@@ -231,8 +235,17 @@ struct epi_batch {
   int running = 0;
 };
 
+// j-axis pass of a slot with per-slice operators: one product per tile (dir 2)
+static void use_zop(const SlotHost& s, GemmArgs& g) {
+  if (!s.zop) return;
+  g.dir = 2;
+  g.A1 = s.zop;
+  g.A2 = nullptr;
+  g.a_bstride = 2LL * s.tab.RT2 * s.tab.KS2 * 64;
+}
+
 static void batch_free_slot(SlotHost& s) {
-  void* bufs[] = {s.w, s.t1, s.t2, s.partial, s.hist};
+  void* bufs[] = {s.w, s.t1, s.t2, s.partial, s.hist, s.zop};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_dct_tables(&s.tab);
@@ -384,6 +397,17 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
     return undo(fail(EPI_ENOMEM, "slot buffers"));
   epi_status ts = build_dct_tables(s.m2, s.m3, grid->h[1], grid->h[2], bt->precision, &s.tab);
   if (ts != EPI_OK) return undo(ts);
+  if (bt->precision == EPI_PREC_MIXED && opts->rho_mode == EPI_RHO_FIXED && (s.m2 + 1) / 2 <= 128) {
+    // the j-axis pass of this volume through its per-slice operators, as the single-volume
+    // solver does with a fixed rho
+    const size_t zb = zop_bytes(s.m2, s.m3, s.tab.RT2, s.tab.KS2);
+    if (hipMalloc(&s.zop, zb) != hipSuccess) return undo(fail(EPI_ENOMEM, "slot operators"));
+    if (hipMemsetAsync(s.zop, 0, zb, bt->exec) != hipSuccess ||
+        launch_build_zop(bt->exec, s.m2, s.m3, grid->h[1], grid->h[2], grid->alpha, opts->rho,
+                         s.tab.RT2, s.tab.KS2, s.zop) != 0 ||
+        hipGetLastError() != hipSuccess)
+      return undo(fail(EPI_EHIP, "slot operator build"));
+  }
   // feasibility of the starting field and the slot's stopping state
   batch_enter(bt);
   DevState* dst = bt->d_st + sid;
@@ -455,6 +479,7 @@ static epi_status batch_rebuild(epi_batch* bt, BatchKey* key) {
     if (three) {
       d.g1 = make_gemm_axis3(s.M, s.m2, s.m3, alpha, s.tab, s.w, s.t1, false, d.st);
       d.g2 = make_gemm_axis2(s.M, s.m2, s.m3, alpha, s.tab, s.t1, s.t2, d.st);
+      use_zop(s, d.g2);
       d.g3 = make_gemm_axis3(s.M, s.m2, s.m3, alpha, s.tab, s.t2, s.z, true, d.st);
       d.g3.epi = 1;
       d.g3.b = s.b;
@@ -468,6 +493,7 @@ static epi_status batch_rebuild(epi_batch* bt, BatchKey* key) {
       add(h->dt[6 + small3], d.g3.nbatch * d.g3.col_tiles);
     } else {
       d.g2 = make_gemm_axis2(s.M, s.m2, s.m3, alpha, s.tab, s.w, s.z, d.st);
+      use_zop(s, d.g2);
       d.g2.epi = 1;
       d.g2.b = s.b;
       d.g2.z = s.z;

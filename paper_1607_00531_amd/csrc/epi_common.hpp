@@ -68,8 +68,10 @@ struct GemmArgs {
   int nbatch;
   int col_tiles;
   int RT, KS;        // 16-row tiles and contraction steps of the packed matrices
-  int dir;           // unfused split-bfloat16 pass: 0 forward, 1 inverse
+  int dir;           // unfused split-bfloat16 pass: 0 forward, 1 inverse, 2 per-batch
+                     // operator (even/odd sums and differences in, even/odd halves out)
   const void* A1;    // packed forward matrix fragments
+  long long a_bstride;  // dir 2: 16-byte fragments per batch entry of A1 (hi and lo blocks)
   const void* A2;    // packed inverse matrix fragments (fused pass only)
   const float* lam_row;    // eigenvalues along the transformed axis (fused pass)
   const float* lam_batch;  // eigenvalues along the batch axis (fused pass), may be null

@@ -69,6 +69,81 @@ void launch_dct_axis2_fused(hipStream_t s, int prec, const GemmArgs& g) {
   launch_dct<true>(s, prec, g);
 }
 
+// ------------------------------------------------------------------------------------
+// Per-slice operator of the j-axis pass for a fixed rho (split-bfloat16). With the
+// even/odd split, the fused pass maps the sums s and differences d of slice k through
+// forward, spectral scale and inverse: E = C_e^T S_e C_e s and O = C_o^T S_o C_o d, with
+// C_h[r][q] = C[2r+h][q] (q, r < c for h = 0, < f for h = 1) and
+// S_h = diag(rho / (rho + alpha (lambda_2(2r+h) + lambda_3(k)))) (eq. dctdiag restricted to
+// one slice). M_h = C_h^T S_h C_h is built here in float64 (C in float32 in LDS, products
+// and sums in float64) and packed as hi/lo bfloat16 fragments in the layout of the forward
+// matrix (row tile rt, contraction step ks), one block of 2 * RT * KS * 64 fragments per
+// slice; padding entries stay zero (the buffer is cleared once when allocated).
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ double dct_eig(int k, int m, double h) {
+  return (2.0 - 2.0 * cos(M_PI * k / m)) / (h * h);
+}
+
+#define ZOP_MAXC 128   // half length limit (transform length <= 256)
+
+__global__ __launch_bounds__(256) void k_build_zop(int m2, int m3, double h2, double h3,
+                                                   double alpha, double rho, int RT, int KS,
+                                                   unsigned short* __restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) double zop_lds[];
+  double* sc = zop_lds;                                   // [ZOP_MAXC]
+  float* Ch = reinterpret_cast<float*>(zop_lds + ZOP_MAXC);   // [cnt][cnt]
+  const int kb = blockIdx.x, h = blockIdx.y;
+  const int ce = (m2 + 1) / 2, fo = m2 / 2, cnt = h ? fo : ce;
+  const int RTh = RT / 2;
+  // spectral index of slice kb along axis 3 (slices are stored in half order)
+  const int ce3 = (m3 + 1) / 2;
+  const int k3 = kb < ce3 ? 2 * kb : 2 * (kb - ce3) + 1;
+  const double lam3 = dct_eig(k3, m3, h3);
+  for (int r = threadIdx.x; r < cnt; r += blockDim.x)
+    sc[r] = rho / (rho + alpha * (dct_eig(2 * r + h, m2, h2) + lam3));
+  for (int e = threadIdx.x; e < cnt * cnt; e += blockDim.x) {
+    const int r = e / cnt, q = e - r * cnt, k = 2 * r + h;
+    const double nrm = k == 0 ? sqrt(1.0 / m2) : sqrt(2.0 / m2);
+    Ch[e] = (float)(nrm * cos(M_PI * k * (2.0 * q + 1.0) / (2.0 * m2)));
+  }
+  __syncthreads();
+  const size_t nfr = (size_t)RT * KS * 64 * 8;
+  unsigned short* o = out + (size_t)kb * 2 * nfr;
+  for (int e = threadIdx.x; e < cnt * cnt; e += blockDim.x) {
+    const int row = e / cnt, q = e - row * cnt;
+    double acc = 0.0;
+    for (int r = 0; r < cnt; ++r) acc += (double)Ch[r * cnt + row] * sc[r] * (double)Ch[r * cnt + q];
+    const int rt = h * RTh + row / 16, ks = q / 32, l = (row & 15) + 16 * ((q & 31) >> 3);
+    const size_t idx = (((size_t)rt * KS + ks) * 64 + l) * 8 + (q & 7);
+    const unsigned short hi = bf16_rne((float)acc);
+    const unsigned short lo = bf16_rne((float)(acc - (double)__uint_as_float((unsigned)hi << 16)));
+    o[idx] = hi;
+    o[nfr + idx] = lo;
+  }
+}
+
+size_t zop_bytes(int m2, int m3, int RT, int KS) {
+  return (size_t)m3 * 2 * RT * KS * 64 * 8 * sizeof(unsigned short);
+}
+
+int launch_build_zop(hipStream_t s, int m2, int m3, double h2, double h3, double alpha,
+                     double rho, int RT, int KS, unsigned short* out) {
+  if ((m2 + 1) / 2 > ZOP_MAXC) return 1;
+  const int ce = (m2 + 1) / 2;
+  const size_t lds = ZOP_MAXC * sizeof(double) + (size_t)ce * ce * sizeof(float);
+  hipLaunchKernelGGL(k_build_zop, dim3(m3, 2), dim3(256), lds, s, m2, m3, h2, h3, alpha, rho,
+                     RT, KS, out);
+  return 0;
+}
+
+void launch_dct_axis2_op(hipStream_t s, int prec, const GemmArgs& g) { launch_dct<false>(s, prec, g); }
+
 // Kernels need more than 64 KB of dynamic LDS for the largest tiles.
 template <bool FUSED, int EPI, int KSM, int SLOTS>
 static bool set_lds(int big) {
@@ -86,6 +161,9 @@ int dct_set_lds_limits() {
   bad |= set_lds<false, 1, 8, 4>(big);
   bad |= set_lds<true, 0, 8, 4>(big);
   bad |= set_lds<true, 1, 8, 4>(big);
+  bad |= hipSuccess != hipFuncSetAttribute((const void*)k_build_zop,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           ZOP_MAXC * sizeof(double) + ZOP_MAXC * ZOP_MAXC * sizeof(float));
   (void)hipGetLastError();
   return bad ? 1 : 0;
 }

@@ -288,6 +288,8 @@ __device__ __forceinline__ void acc_rows_to_lds(float* T, const f4 (&acc)[SLOTS]
 // tile's partial sums (EPI 1). Every thread of the workgroup (NW wavefronts) must call it.
 // FUSED: spatial in, forward, spectral scale, inverse, spatial out; otherwise g.dir = 0
 // (spatial in, spectral out in half order) or 1 (spectral in half order, spatial out).
+// g.dir = 2 (either instantiation): spatial in and out through one product with the batch
+// entry's own even/odd operator, which stands for forward, spectral scale and inverse.
 template <bool FUSED, int EPI, int KSF, int NW>
 __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int c0, int pslot,
                                               unsigned short* lds_bf) {
@@ -301,7 +303,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
   const int KPh = g.KS * 32;                       // contraction extent of one half
   const int KP = 2 * KPh + EPI_DCT_KPAD;
   const int RTh = g.RT / 2;
-  const bool fwd_in = FUSED || g.dir == 0;
+  const bool fwd_in = FUSED || g.dir != 1;
   unsigned short* Lhi = lds_bf;
   unsigned short* Llo = lds_bf + DCT_NT * KP;
   float* SC = reinterpret_cast<float*>(reinterpret_cast<char*>(lds_bf) + dct_tile_bytes(1, g));
@@ -333,7 +335,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
         vb[it][e] = okb ? ld_at<float>(in + (size_t)(okb ? rb : 0) * g.ld, lane4) : 0.0f;
       }
     }
-    if (FUSED) {
+    if (FUSED && g.dir != 2) {
       // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)) of each row tile row
       // in half order (0 beyond the half's length), read after the first product
       const int hr = RTh * 16, rows = 2 * hr;
@@ -390,10 +392,11 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[s][ct] = f4{0.f, 0.f, 0.f, 0.f};
   const size_t frag_stride = (size_t)g.RT * g.KS * 64;   // hi block, then lo block
-  gemm_bf16<SLOTS, KSM, GemmPD<KSM>::value>(reinterpret_cast<const us8*>(g.A1), frag_stride, g.KS,
-                                            rt0, HW, lane, nslot, Lhi, Llo, KP, koff, acc);
+  const us8* A1 = reinterpret_cast<const us8*>(g.A1) + (size_t)batch * g.a_bstride;
+  gemm_bf16<SLOTS, KSM, GemmPD<KSM>::value>(A1, frag_stride, g.KS, rt0, HW, lane, nslot, Lhi,
+                                            Llo, KP, koff, acc);
 
-  if (FUSED) {
+  if (FUSED && g.dir != 2) {
     // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)) in half order, then
     // the inverse from the same LDS blocks
     const float* sch = SC + half * RTh * 16;
@@ -430,7 +433,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
   float* T = reinterpret_cast<float*>(lds_bf);
   acc_rows_to_lds<SLOTS>(T, acc, rt0, HW, lane, nslot);
   __syncthreads();
-  if (FUSED || g.dir == 1)
+  if (FUSED || g.dir != 0)
     tile_epilogue<EPI, NW, OUT_EVEN_ODD>(g, T, bofs, c0, pslot, RTh * 16);
   else
     tile_epilogue<EPI, NW, OUT_HALF_ORDER>(g, T, bofs, c0, pslot, RTh * 16);

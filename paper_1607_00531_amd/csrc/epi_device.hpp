@@ -224,22 +224,30 @@ __device__ __forceinline__ void stage_in(const float* __restrict__ src, int coun
   __syncthreads();
 }
 
-// NA arrays at once: every global load is issued before the first LDS write, so one
-// memory round trip covers all of them. lds holds NA consecutive LineBuf<P> buffers.
+// Global -> registers in the lane-contiguous layout, NA arrays: t[a][j] = src[a][lane + 64 j]
+// for indices < count[a], else 0. P = ceil((M + 1) / 64) and count >= M, so only the last
+// of the P loads can fall past the end of a line; it reads the line's last element instead
+// (in bounds) and the value is replaced by 0, so every load is unconditional and all of
+// them are issued back to back. src must point at a valid line also when valid is false.
 template <int P, int NA>
-__device__ __forceinline__ void stage_in_n(const float* const (&src)[NA], const int (&count)[NA],
-                                           bool valid, float* lds, float (&dst)[NA][P],
-                                           int lane) {
-  // P = ceil((M + 1) / 64) and count >= M, so only the last of the P loads can fall past
-  // the end of a line: the others are unconditional (given valid).
-  float t[NA][P];
+__device__ __forceinline__ void load_line_n(const float* const (&src)[NA], const int (&count)[NA],
+                                            bool valid, float (&t)[NA][P], int lane) {
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const int i = lane + 64 * j;
-      t[a][j] = (valid && (j < P - 1 || i < count[a])) ? src[a][i] : 0.0f;
+      const bool in = j < P - 1 || i < count[a];
+      const float x = src[a][in ? i : count[a] - 1];
+      t[a][j] = (valid && in) ? x : 0.0f;
     }
+}
+
+// Lane-contiguous registers -> LDS (NA consecutive LineBuf<P> buffers, which keep the
+// line) -> lane-blocked registers dst[a][j] = line a at P * lane + j.
+template <int P, int NA>
+__device__ __forceinline__ void regs_to_blocked_n(const float (&t)[NA][P], float* lds,
+                                                  float (&dst)[NA][P], int lane) {
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -250,6 +258,17 @@ __device__ __forceinline__ void stage_in_n(const float* const (&src)[NA], const 
 #pragma unroll
     for (int j = 0; j < P; ++j) dst[a][j] = lds[a * LineBuf<P>::SIZE + lds_pad(P * lane + j)];
   __syncthreads();
+}
+
+// NA arrays at once: every global load is issued before the first LDS write, so one
+// memory round trip covers all of them. lds holds NA consecutive LineBuf<P> buffers.
+template <int P, int NA>
+__device__ __forceinline__ void stage_in_n(const float* const (&src)[NA], const int (&count)[NA],
+                                           bool valid, float* lds, float (&dst)[NA][P],
+                                           int lane) {
+  float t[NA][P];
+  load_line_n<P, NA>(src, count, valid, t, lane);
+  regs_to_blocked_n<P, NA>(t, lds, dst, lane);
 }
 
 // NA arrays out at once (one barrier pair for all of them).
