@@ -44,11 +44,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def mfma_flops(M, m2, m3, precision):
+def mfma_flops(M, m2, m3, precision, fixed_rho=True):
     """Matrix-core flops each DCT pass executes over the unpadded transform lengths. The
     split-bf16 path runs the even/odd halves of each transform (2c^2 + 2f^2 per column of
     length m, c = ceil(m/2), f = floor(m/2)) with three products per multiply-add; the
-    float32 path runs full products (2m^2 per column)."""
+    float32 path runs full products (2m^2 per column). The j-axis pass applies forward and
+    inverse (two products), except in split-bf16 with a fixed rho, where it is one product
+    with the per-slice operator of the same half-block shape."""
     n = (M + 1) * m2 * m3
 
     def per_face(m):
@@ -57,7 +59,8 @@ def mfma_flops(M, m2, m3, precision):
             return 3 * (2 * c * c + 2 * f * f) / m
         return 2 * m
 
-    return {"dct_axis3": per_face(m3) * n, "dct_axis2_fused": 2 * per_face(m2) * n,
+    j = 1 if (precision == "mixed" and fixed_rho) else 2
+    return {"dct_axis3": per_face(m3) * n, "dct_axis2_fused": j * per_face(m2) * n,
             "dct_last_epilogue": per_face(m3) * n}
 
 

@@ -26,16 +26,20 @@ def test_algorithmic_bytes_of_the_admm_kernels():
 
 def test_mfma_flops_of_the_split_transform():
     """Even/odd halves: 2c^2 + 2f^2 per column of length m (c, f the half lengths), three
-    products per multiply-add in mixed precision; full 2m^2 per column in float32."""
+    products per multiply-add in mixed precision; full 2m^2 per column in float32. The j-axis
+    pass is one product with a fixed rho in mixed precision (per-slice operator), two
+    otherwise."""
     import bench
     M, m2, m3 = 240, 200, 110
     n = (M + 1) * m2 * m3
     mixed, fp32 = bench.mfma_flops(M, m2, m3, "mixed"), bench.mfma_flops(M, m2, m3, "fp32")
     assert mixed["dct_axis3"] == 3 * (2 * 55 * 55 * 2) / 110 * n
-    assert mixed["dct_axis2_fused"] == 2 * 3 * (2 * 100 * 100 * 2) / 200 * n
+    assert mixed["dct_axis2_fused"] == 3 * (2 * 100 * 100 * 2) / 200 * n
+    adaptive = bench.mfma_flops(M, m2, m3, "mixed", fixed_rho=False)
+    assert adaptive["dct_axis2_fused"] == 2 * mixed["dct_axis2_fused"]
     assert fp32["dct_axis2_fused"] == 2 * 2 * m2 * n
     odd = bench.mfma_flops(10, 7, 5, "mixed")        # odd lengths: c = 4, f = 3 for m = 7
-    assert odd["dct_axis2_fused"] == 2 * 3 * (2 * 16 + 2 * 9) / 7 * (11 * 7 * 5)
+    assert odd["dct_axis2_fused"] == 3 * (2 * 16 + 2 * 9) / 7 * (11 * 7 * 5)
 
 
 def test_counter_traffic_keys_on_the_kernel_sources():
