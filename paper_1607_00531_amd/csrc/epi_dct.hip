@@ -92,14 +92,24 @@ __device__ __forceinline__ double dct_eig(int k, int m, double h) {
 
 #define ZOP_MAXC 128   // half length limit (transform length <= 256)
 
+// packed position of (row, contraction index q) of half h in one slice's hi block
+__device__ __forceinline__ size_t zop_index(int h, int row, int q, int RTh, int KS) {
+  const int rt = h * RTh + row / 16, ks = q / 32, l = (row & 15) + 16 * ((q & 31) >> 3);
+  return (((size_t)rt * KS + ks) * 64 + l) * 8 + (q & 7);
+}
+
+// One workgroup per (slice, half). Each thread accumulates 4 x 4 blocks of M_h (rows
+// 4 bi.., columns 4 bj.., bi <= bj; M_h is symmetric, the mirror is written from the same
+// sums) over r, with C_h zero-padded to a multiple of 4 in LDS.
 __global__ __launch_bounds__(256) void k_build_zop(int m2, int m3, double h2, double h3,
                                                    double alpha, double rho, int RT, int KS,
                                                    unsigned short* __restrict__ out) {
   extern __shared__ __attribute__((aligned(16))) double zop_lds[];
-  double* sc = zop_lds;                                   // [ZOP_MAXC]
-  float* Ch = reinterpret_cast<float*>(zop_lds + ZOP_MAXC);   // [cnt][cnt]
+  double* sc = zop_lds;                                       // [ZOP_MAXC]
+  float* Ch = reinterpret_cast<float*>(zop_lds + ZOP_MAXC);   // [cnt][cp]
   const int kb = blockIdx.x, h = blockIdx.y;
   const int ce = (m2 + 1) / 2, fo = m2 / 2, cnt = h ? fo : ce;
+  const int cp = (cnt + 3) & ~3, nb = cp / 4;
   const int RTh = RT / 2;
   // spectral index of slice kb along axis 3 (slices are stored in half order)
   const int ce3 = (m3 + 1) / 2;
@@ -107,24 +117,57 @@ __global__ __launch_bounds__(256) void k_build_zop(int m2, int m3, double h2, do
   const double lam3 = dct_eig(k3, m3, h3);
   for (int r = threadIdx.x; r < cnt; r += blockDim.x)
     sc[r] = rho / (rho + alpha * (dct_eig(2 * r + h, m2, h2) + lam3));
-  for (int e = threadIdx.x; e < cnt * cnt; e += blockDim.x) {
-    const int r = e / cnt, q = e - r * cnt, k = 2 * r + h;
+  for (int e = threadIdx.x; e < cnt * cp; e += blockDim.x) {
+    const int r = e / cp, q = e - r * cp, k = 2 * r + h;
     const double nrm = k == 0 ? sqrt(1.0 / m2) : sqrt(2.0 / m2);
-    Ch[e] = (float)(nrm * cos(M_PI * k * (2.0 * q + 1.0) / (2.0 * m2)));
+    Ch[e] = q < cnt ? (float)(nrm * cos(M_PI * k * (2.0 * q + 1.0) / (2.0 * m2))) : 0.0f;
   }
   __syncthreads();
   const size_t nfr = (size_t)RT * KS * 64 * 8;
   unsigned short* o = out + (size_t)kb * 2 * nfr;
-  for (int e = threadIdx.x; e < cnt * cnt; e += blockDim.x) {
-    const int row = e / cnt, q = e - row * cnt;
-    double acc = 0.0;
-    for (int r = 0; r < cnt; ++r) acc += (double)Ch[r * cnt + row] * sc[r] * (double)Ch[r * cnt + q];
-    const int rt = h * RTh + row / 16, ks = q / 32, l = (row & 15) + 16 * ((q & 31) >> 3);
-    const size_t idx = (((size_t)rt * KS + ks) * 64 + l) * 8 + (q & 7);
-    const unsigned short hi = bf16_rne((float)acc);
-    const unsigned short lo = bf16_rne((float)(acc - (double)__uint_as_float((unsigned)hi << 16)));
-    o[idx] = hi;
-    o[nfr + idx] = lo;
+  const int ntask = nb * (nb + 1) / 2;
+  for (int t = threadIdx.x; t < ntask; t += blockDim.x) {
+    // task t -> (bi, bj) with bi <= bj, row-major over the upper triangle
+    int bi = 0, rem = t;
+    while (rem >= nb - bi) {
+      rem -= nb - bi;
+      ++bi;
+    }
+    const int bj = bi + rem;
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int r = 0; r < cnt; ++r) {
+      const float4 x = *reinterpret_cast<const float4*>(&Ch[r * cp + 4 * bi]);
+      const float4 y = *reinterpret_cast<const float4*>(&Ch[r * cp + 4 * bj]);
+      const double s = sc[r];
+      const double xs[4] = {x.x * s, x.y * s, x.z * s, x.w * s};
+      const double yv[4] = {y.x, y.y, y.z, y.w};
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(xs[a], yv[b], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int row = 4 * bi + a, q = 4 * bj + b;
+        if (row >= cnt || q >= cnt) continue;
+        const unsigned short hi = bf16_rne((float)acc[a][b]);
+        const unsigned short lo =
+            bf16_rne((float)(acc[a][b] - (double)__uint_as_float((unsigned)hi << 16)));
+        const size_t i1 = zop_index(h, row, q, RTh, KS);
+        o[i1] = hi;
+        o[nfr + i1] = lo;
+        if (row != q) {
+          const size_t i2 = zop_index(h, q, row, RTh, KS);
+          o[i2] = hi;
+          o[nfr + i2] = lo;
+        }
+      }
   }
 }
 
@@ -135,8 +178,8 @@ size_t zop_bytes(int m2, int m3, int RT, int KS) {
 int launch_build_zop(hipStream_t s, int m2, int m3, double h2, double h3, double alpha,
                      double rho, int RT, int KS, unsigned short* out) {
   if ((m2 + 1) / 2 > ZOP_MAXC) return 1;
-  const int ce = (m2 + 1) / 2;
-  const size_t lds = ZOP_MAXC * sizeof(double) + (size_t)ce * ce * sizeof(float);
+  const int ce = (m2 + 1) / 2, cp = (ce + 3) & ~3;
+  const size_t lds = ZOP_MAXC * sizeof(double) + (size_t)ce * cp * sizeof(float);
   hipLaunchKernelGGL(k_build_zop, dim3(m3, 2), dim3(256), lds, s, m2, m3, h2, h3, alpha, rho,
                      RT, KS, out);
   return 0;
