@@ -64,15 +64,25 @@ def mfma_flops(M, m2, m3, precision, fixed_rho=True):
             "dct_last_epilogue": per_face(m3) * n}
 
 
-def algorithmic_bytes(M, m2, m3):
-    """HBM bytes each kernel family must move per launch (float32 arrays)."""
+def zop_bytes(m2, m3):
+    """Bytes of the split-bf16 per-slice operators of the j-axis pass (fixed rho): hi and lo
+    bfloat16 fragments of both even/odd halves, padded to 16-row tiles and 32-wide steps."""
+    ce = (m2 + 1) // 2
+    rt, ks = 2 * ((ce + 15) // 16), (ce + 31) // 32
+    return m3 * 2 * rt * ks * 64 * 8 * 2
+
+
+def algorithmic_bytes(M, m2, m3, zop=True):
+    """HBM bytes each kernel family must move per launch (float32 arrays). zop: the j-axis
+    pass also reads its per-slice operators (split-bf16 solver with a fixed rho)."""
     n = (M + 1) * m2 * m3
     N = M * m2 * m3
     last = 24 * n                                  # read T, b, u, z_old; write z, u
     return {
         "bstep": 4 * (2 * N + 5 * n),              # read I+, I-, b, z, u; write b, w
         "dct_axis3": 8 * n,                        # read w, write T1
-        "dct_axis2_fused": 8 * n,                  # read T1, write T2 (3D) / epilogue (2D)
+        # read T1, write T2 (3D) / epilogue (2D); + the operators
+        "dct_axis2_fused": 8 * n + (zop_bytes(m2, m3) if zop else 0),
         "dct_last_epilogue": last,
         "bstep_hard": 0, "finalize": 0,
     }

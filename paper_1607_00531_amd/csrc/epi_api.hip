@@ -79,7 +79,8 @@ struct epi_problem {
   int hard_blocks = 0;
   // DCT tables (packed MFMA fragments), eigenvalues
   DctTables tab;
-  // per-slice j-axis operators for one fixed rho (split-bfloat16; zop_rho 0: not built)
+  // per-slice j-axis operators for one fixed rho (split-bfloat16, inside the t2 allocation;
+  // zop_rho 0: not built)
   unsigned short* zop = nullptr;
   double zop_rho = 0.0;
   bool use_zop = false;
@@ -339,7 +340,7 @@ EPI_API void epi_destroy(epi_problem* p) {
   if (p->exec) (void)hipStreamSynchronize(p->exec);
   free_graph(p);
   void* bufs[] = {p->w, p->t1, p->t2, p->g, p->hd, p->ho, p->x, p->r, p->zz, p->p, p->q,
-                  p->partial, p->partial_e, p->st, p->hard_list, p->hist, p->zop};
+                  p->partial, p->partial_e, p->st, p->hard_list, p->hist};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_dct_tables(&p->tab);
@@ -430,8 +431,15 @@ static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float*
   HIPCHK(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
   const size_t nb = (size_t)p->n * sizeof(float);
+  // split-bfloat16 problems keep the per-slice operators of the j-axis pass behind t2
+  const size_t nb_al = (nb + 255) & ~(size_t)255;
+  const int ce2 = (p->m2 + 1) / 2;
+  const size_t zb = (grid->precision == EPI_PREC_MIXED && ce2 <= 128)
+                        ? zop_bytes(p->m2, p->m3, 2 * ((ce2 + 15) / 16), (ce2 + 31) / 32)
+                        : 0;
   float** bufs[] = {&p->w, &p->t1, &p->t2, &p->g, &p->hd, &p->ho, &p->x, &p->r, &p->zz, &p->p, &p->q};
-  for (float** b : bufs) HIPCHK(hipMalloc(b, nb));
+  for (float** b : bufs) HIPCHK(hipMalloc(b, b == &p->t2 ? nb_al + zb : nb));
+  if (zb) p->zop = reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(p->t2) + nb_al);
   const int lb = line_blocks(a);
   p->hard_blocks = p->L < 128 ? p->L : 128;
   size_t cap = (size_t)lb * NQ_EVAL;
@@ -616,13 +624,9 @@ static void launch_axis2(const epi_problem* p, int prec, const GemmArgs& g) {
 // once per rho); with an adaptive rho, or in float32, the fused pass applies the three.
 static epi_status prepare_zop(epi_problem* p, double rho, bool fixed_rho) {
   p->use_zop = false;
-  if (p->grid.precision != EPI_PREC_MIXED || !fixed_rho || (p->m2 + 1) / 2 > 128) return EPI_OK;
-  if (!p->zop) {
-    const size_t bytes = zop_bytes(p->m2, p->m3, p->tab.RT2, p->tab.KS2);
-    HIPCHK(hipMalloc(&p->zop, bytes));
-    HIPCHK(hipMemsetAsync(p->zop, 0, bytes, p->exec));
-    p->zop_rho = 0.0;
-  }
+  if (!p->zop || !fixed_rho) return EPI_OK;   // zop: split-bfloat16 problems only
+  if (p->zop_rho == 0.0)   // padding entries of the fragments stay zero
+    HIPCHK(hipMemsetAsync(p->zop, 0, zop_bytes(p->m2, p->m3, p->tab.RT2, p->tab.KS2), p->exec));
   if (p->zop_rho != rho) {
     if (launch_build_zop(p->exec, p->m2, p->m3, p->grid.h[1], p->grid.h[2], p->grid.alpha, rho,
                          p->tab.RT2, p->tab.KS2, p->zop))

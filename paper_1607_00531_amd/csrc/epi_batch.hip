@@ -99,10 +99,16 @@ __global__ __launch_bounds__(PREC == 1 ? 64 * EPI_DCT_NW : 256) void k_batch_dct
   const int batch = local / g.col_tiles;
   const int c0 = (local % g.col_tiles) * DCT_NT;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-  if (PREC == 1)
-    dct_bf16_body<FUSED, EPI, KSM, EPI_DCT_NW>(g, batch, c0, local,
-                                          reinterpret_cast<unsigned short*>(lds_raw));
-  else
+  if (PREC == 1) {
+    // a fixed-rho slot's j-axis pass goes through its per-slice operators (dir 2, the
+    // unfused body): a separate inlined body, so each keeps its own register budget
+    if (FUSED && g.dir == 2)
+      dct_bf16_body<false, EPI, KSM, EPI_DCT_NW>(g, batch, c0, local,
+                                                 reinterpret_cast<unsigned short*>(lds_raw));
+    else
+      dct_bf16_body<FUSED, EPI, KSM, EPI_DCT_NW>(g, batch, c0, local,
+                                                 reinterpret_cast<unsigned short*>(lds_raw));
+  } else
     dct_f32_body<FUSED, EPI, KSM * 8, SLOTS>(g, batch, c0, local,
                                              reinterpret_cast<float*>(lds_raw));
 }
@@ -187,7 +193,8 @@ struct SlotHost {
   double* hist = nullptr;
   int hist_len = 0;
   DctTables tab;
-  unsigned short* zop = nullptr;   // per-slice j-axis operators (split-bfloat16, fixed rho)
+  unsigned short* zop = nullptr;   // per-slice j-axis operators (split-bfloat16, fixed rho;
+                                   // inside the t2 allocation)
   int64_t footprint = 0;
   epi_admm_opts opts{};
 };
@@ -245,7 +252,7 @@ static void use_zop(const SlotHost& s, GemmArgs& g) {
 }
 
 static void batch_free_slot(SlotHost& s) {
-  void* bufs[] = {s.w, s.t1, s.t2, s.partial, s.hist, s.zop};
+  void* bufs[] = {s.w, s.t1, s.t2, s.partial, s.hist};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_dct_tables(&s.tab);
@@ -387,8 +394,15 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
     return st;
   };
   const size_t nb = (size_t)s.n * sizeof(float);
+  // a fixed-rho split-bfloat16 volume takes its j-axis pass through per-slice operators (as
+  // the single-volume solver does), kept behind t2
+  const size_t nb_al = (nb + 255) & ~(size_t)255;
+  const int ce2 = (s.m2 + 1) / 2;
+  const size_t zb = (bt->precision == EPI_PREC_MIXED && opts->rho_mode == EPI_RHO_FIXED && ce2 <= 128)
+                        ? zop_bytes(s.m2, s.m3, 2 * ((ce2 + 15) / 16), (ce2 + 31) / 32)
+                        : 0;
   if (hipMalloc(&s.w, nb) != hipSuccess || hipMalloc(&s.t1, nb) != hipSuccess ||
-      hipMalloc(&s.t2, nb) != hipSuccess)
+      hipMalloc(&s.t2, nb_al + zb) != hipSuccess)
     return undo(fail(EPI_ENOMEM, "slot workspace"));
   const long long tiles = std::max(tiles_axis3(s.M, s.m2), tiles_axis2(s.M, s.m3));
   const size_t part = (size_t)std::max<long long>(tiles * NQ_ADMM_E, 4096);
@@ -397,11 +411,8 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
     return undo(fail(EPI_ENOMEM, "slot buffers"));
   epi_status ts = build_dct_tables(s.m2, s.m3, grid->h[1], grid->h[2], bt->precision, &s.tab);
   if (ts != EPI_OK) return undo(ts);
-  if (bt->precision == EPI_PREC_MIXED && opts->rho_mode == EPI_RHO_FIXED && (s.m2 + 1) / 2 <= 128) {
-    // the j-axis pass of this volume through its per-slice operators, as the single-volume
-    // solver does with a fixed rho
-    const size_t zb = zop_bytes(s.m2, s.m3, s.tab.RT2, s.tab.KS2);
-    if (hipMalloc(&s.zop, zb) != hipSuccess) return undo(fail(EPI_ENOMEM, "slot operators"));
+  if (zb) {
+    s.zop = reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(s.t2) + nb_al);
     if (hipMemsetAsync(s.zop, 0, zb, bt->exec) != hipSuccess ||
         launch_build_zop(bt->exec, s.m2, s.m3, grid->h[1], grid->h[2], grid->alpha, opts->rho,
                          s.tab.RT2, s.tab.KS2, s.zop) != 0 ||

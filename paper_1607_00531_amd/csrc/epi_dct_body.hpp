@@ -287,9 +287,9 @@ __device__ __forceinline__ void acc_rows_to_lds(float* T, const f4 (&acc)[SLOTS]
 // One 64-column tile of one batch entry: fill, product(s), epilogue. pslot = index of this
 // tile's partial sums (EPI 1). Every thread of the workgroup (NW wavefronts) must call it.
 // FUSED: spatial in, forward, spectral scale, inverse, spatial out; otherwise g.dir = 0
-// (spatial in, spectral out in half order) or 1 (spectral in half order, spatial out).
-// g.dir = 2 (either instantiation): spatial in and out through one product with the batch
-// entry's own even/odd operator, which stands for forward, spectral scale and inverse.
+// (spatial in, spectral out in half order), 1 (spectral in half order, spatial out) or 2
+// (spatial in and out through one product with the batch entry's own even/odd operator,
+// which stands for forward, spectral scale and inverse together).
 template <bool FUSED, int EPI, int KSF, int NW>
 __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int c0, int pslot,
                                               unsigned short* lds_bf) {
@@ -335,7 +335,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
         vb[it][e] = okb ? ld_at<float>(in + (size_t)(okb ? rb : 0) * g.ld, lane4) : 0.0f;
       }
     }
-    if (FUSED && g.dir != 2) {
+    if (FUSED) {
       // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)) of each row tile row
       // in half order (0 beyond the half's length), read after the first product
       const int hr = RTh * 16, rows = 2 * hr;
@@ -396,7 +396,7 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
   gemm_bf16<SLOTS, KSM, GemmPD<KSM>::value>(A1, frag_stride, g.KS, rt0, HW, lane, nslot, Lhi,
                                             Llo, KP, koff, acc);
 
-  if (FUSED && g.dir != 2) {
+  if (FUSED) {
     // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)) in half order, then
     // the inverse from the same LDS blocks
     const float* sch = SC + half * RTh * 16;
