@@ -26,8 +26,10 @@ __device__ __forceinline__ void chunk_of(long long n, long long& lo, long long& 
 // q = H_JGN p = (line tridiagonal) p + alpha v (D2'D2 + D3'D3) p  (eq. dJGN, Section 3:
 // the transverse coupling of the regulariser is a Neumann Laplacian stencil); partial p.q.
 // One wavefront per PE line (lane-contiguous faces, 32-bit index arithmetic); the
-// neighbours along the line come from the same cache lines, those of the neighbouring
-// lines (j +- 1, k +- 1) from L2.
+// neighbours along the line come from lane shifts. The four wavefronts of a workgroup hold
+// four consecutive lines and share them through LDS, so the j +- 1 neighbours of the inner
+// lines are read there; the other neighbour lines (j +- 1 at the workgroup's ends, k +- 1)
+// come from L2.
 // DIR: the PCG direction update is fused in: p = z + beta p_old is formed on the fly at
 // every stencil point (the same value the separate update computes), written to pnew, and
 // q = H p; otherwise p = pold.
@@ -40,6 +42,7 @@ __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restr
                                                 float* __restrict__ q, double* partial,
                                                 const DevState* st) {
   if (st->pcg_done) return;
+  __shared__ float sp[EPI_LINE_WAVES][64 * P];   // p of the workgroup's lines, face order
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = xcd_remap(blockIdx.x, a.nblk);
   const int line = blk * EPI_LINE_WAVES + wave;
@@ -64,9 +67,14 @@ __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restr
     const int i = lane + 64 * j;
     const bool ok = lv && (j < P - 1 || i < NF);
     pc[j] = ok ? pat(i) : 0.0f;
+    sp[wave][i] = pc[j];
     hdv[j] = ok ? hd[base + i] : 0.0f;
     hov[j] = ok ? ho[base + i] : 0.0f;
   }
+  __syncthreads();
+  // line - 1 / line + 1 of this workgroup (the same k-plane whenever the neighbour exists)
+  const float* spm = wave > 0 ? sp[wave - 1] : nullptr;
+  const float* spp = wave < EPI_LINE_WAVES - 1 ? sp[wave + 1] : nullptr;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int i = lane + 64 * j;
@@ -89,8 +97,8 @@ __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restr
       if (i > 0) y = fmaf(ho_p, pp, y);
       if (i < NF - 1) y = fmaf(hov[j], pn, y);
       float l2 = 0.0f, l3 = 0.0f;
-      if (j0) l2 += pc[j] - pat(i - NF);
-      if (j1) l2 += pc[j] - pat(i + NF);
+      if (j0) l2 += pc[j] - (spm ? spm[i] : pat(i - NF));
+      if (j1) l2 += pc[j] - (spp ? spp[i] : pat(i + NF));
       if (k0) l3 += pc[j] - pat(i - plane);
       if (k1) l3 += pc[j] - pat(i + plane);
       y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
