@@ -27,14 +27,14 @@ from tests.gpu_common import T, N, J_REL, FIELD_VOX, hist_ok, oracle_precond, pr
 
 pytestmark = pytest.mark.gpu
 
-C3 = "3d_240x200x110"
-C2 = "3d_128x128x64"
+V240 = "3d_240x200x110"
+V128 = "3d_128x128x64"
 ADMM_ITERS = 4
 
 
 def _problem(v, alpha, prec):
     from paper_1607_00531_amd import Problem
-    return Problem(T(v.Ip), T(v.Im), v.h, alpha, beta=CONFIGS[C3]["beta"], precision=prec)
+    return Problem(T(v.Ip), T(v.Im), v.h, alpha, beta=CONFIGS[V240]["beta"], precision=prec)
 
 
 def _oracle_steps(P, rho, iters):
@@ -54,16 +54,16 @@ def _oracle_steps(P, rho, iters):
 
 @pytest.fixture(scope="module")
 def c3():
-    v = config_volume(C3, 0)
-    alpha, rho = CONFIGS[C3]["alpha"], CONFIGS[C3]["rho"]
+    v = config_volume(V240, 0)
+    alpha, rho = CONFIGS[V240]["alpha"], CONFIGS[V240]["rho"]
     P = O.make_problem(v.Ip, v.Im, v.h, alpha)
     return v, P, _oracle_steps(P, rho, ADMM_ITERS)
 
 
 @pytest.fixture(scope="module")
 def c2():
-    v = config_volume(C2, 0)
-    alpha, rho = CONFIGS[C2]["alpha"], CONFIGS[C2]["rho"]
+    v = config_volume(V128, 0)
+    alpha, rho = CONFIGS[V128]["alpha"], CONFIGS[V128]["rho"]
     P = O.make_problem(v.Ip, v.Im, v.h, alpha)
     gn = O.solve_gnpcg(P, max_iter=2, use_stopping=False)
     return v, P, gn, _oracle_steps(P, rho, ADMM_ITERS)
@@ -76,7 +76,7 @@ def test_c3_shape_is_the_benchmark_workload(c3):
 
 def test_c3_objective_and_gradient(c3):
     v, P, _ = c3
-    alpha = CONFIGS[C3]["alpha"]
+    alpha = CONFIGS[V240]["alpha"]
     with _problem(v, alpha, "mixed") as pr:
         for bb in (v.b_true.reshape(P.L, -1), np.zeros((P.L, P.M + 1))):
             g = T(np.zeros(pr.shape_faces))
@@ -136,13 +136,13 @@ def _check_admm_steps(pr, P, ref, prec):
 @pytest.mark.parametrize("prec", ["mixed", "fp32"])
 def test_c3_admm_steps(c3, prec):
     v, P, ref = c3
-    with _problem(v, CONFIGS[C3]["alpha"], prec) as pr:
+    with _problem(v, CONFIGS[V240]["alpha"], prec) as pr:
         _check_admm_steps(pr, P, ref, prec)
 
 
 def test_c2_gnpcg_steps(c2):
     v, P, (bo, ro), _ = c2
-    with _problem(v, CONFIGS[C2]["alpha"], "mixed") as pr:
+    with _problem(v, CONFIGS[V128]["alpha"], "mixed") as pr:
         b = T(np.zeros(pr.shape_faces))
         rep = pr.solve_gnpcg(b, max_iter=2, use_stopping=0)
         assert rep["iters"] == ro.iters == 2
@@ -154,7 +154,7 @@ def test_c2_gnpcg_steps(c2):
 @pytest.mark.parametrize("prec", ["mixed", "fp32"])
 def test_c2_admm_steps(c2, prec):
     v, P, _, ref = c2
-    with _problem(v, CONFIGS[C2]["alpha"], prec) as pr:
+    with _problem(v, CONFIGS[V128]["alpha"], prec) as pr:
         _check_admm_steps(pr, P, ref, prec)
 
 
@@ -166,7 +166,7 @@ def test_c2_precond_apply(c2, precond):
     r = np.random.default_rng(9).normal(size=(P.L, P.M + 1))
     zo = oracle_precond(P, tri, r, precond)
     tol = precond_tol(P, tri, r, precond, zo)
-    with _problem(v, CONFIGS[C2]["alpha"], "mixed") as pr:
+    with _problem(v, CONFIGS[V128]["alpha"], "mixed") as pr:
         sh = pr.shape_faces
         z = pr.precond_apply(T(b.reshape(sh)), T(r.reshape(sh)), precond)
         err = np.abs(N(z).reshape(P.L, -1) - zo).max() / np.abs(zo).max()
