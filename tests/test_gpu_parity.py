@@ -79,6 +79,31 @@ def test_smooth_solve(shape, pe, prec, tol):
             assert err <= tol, err
 
 
+def test_zstep_operators_follow_rho_across_calls():
+    """The per-slice operators are built for one rho and rebuilt when a call brings another;
+    a captured ADMM chunk reuses the same operator buffer. Interleaving z-steps and ADMM
+    solves at different rho therefore repeats every result bitwise."""
+    v = generate(6, (20, 24, 12), 0, n_blobs=2, n_bumps=1)
+    P = O.make_problem(v.Ip, v.Im, v.h, 3.0)
+    w = T(np.random.default_rng(7).normal(size=P.n))
+    opts = dict(rho=1e3, max_iter=5, eps_abs=0.0, eps_rel=0.0, check_every=5)
+    with _problem(v, 3.0, "mixed") as pr:
+        wf = w.reshape(pr.shape_faces)
+        z1 = N(pr.smooth_solve(wf, 1.0))
+        st_a = [T(np.zeros(pr.shape_faces)) for _ in range(3)]
+        pr.solve_admm(*st_a, **opts)
+        z2 = N(pr.smooth_solve(wf, 1e3))
+        z3 = N(pr.smooth_solve(wf, 1.0))
+        st_b = [T(np.zeros(pr.shape_faces)) for _ in range(3)]
+        pr.solve_admm(*st_b, **opts)
+    np.testing.assert_array_equal(z1, z3)
+    for a, b in zip(st_a, st_b):
+        np.testing.assert_array_equal(N(a), N(b))
+    for rho, z in ((1.0, z1), (1e3, z2)):
+        zo = O.zstep(P, N(w), rho).reshape(-1)
+        assert np.abs(z.reshape(-1) - zo).max() / np.abs(zo).max() <= 5e-5
+
+
 @pytest.mark.parametrize("shape,pe", [((16, 20, 12), 0), ((64, 64), 1), ((20, 70, 9), 1),
                                       ((9, 256, 3), 1), ((12, 5, 40), 1)])
 def test_zstep_operator_and_fused_pass_agree(shape, pe):
