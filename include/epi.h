@@ -201,8 +201,11 @@ epi_status epi_objective(epi_problem* p, const float* d_b, int32_t with_penalty,
 
 /* The non-separable smoothness solve of the ADMM z-step (Section 4.2, eq. dctdiag):
  * d_z = (alpha v (D2'D2 + D3'D3) + rho v I)^{-1} rho v d_w, by the orthonormal 2D DCT over
- * the two non-PE axes in the arithmetic of grid->precision. d_w and d_z are n floats and
- * may alias. Does not synchronise. */
+ * the two non-PE axes in the arithmetic of grid->precision. In split-bfloat16 the
+ * j-axis forward, spectral scale and inverse of each k-slice are applied as one product
+ * with a per-slice operator built on the device for this rho (rebuilt, tens of
+ * microseconds, when rho differs from the last call's). d_w and d_z are n floats and may
+ * alias. Does not synchronise. */
 epi_status epi_smooth_solve(epi_problem* p, const float* d_w, double rho, float* d_z);
 
 /* One application of a GN-PCG preconditioner (Section 4.1, eq. Pblock, eq. Psgs) built
@@ -224,7 +227,9 @@ epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts* opts,
  * state (b^k, z^k, u^k) on entry and on exit, so a solve can be resumed by calling again.
  * The starting b must satisfy |D1 b| <= 1. Every iteration runs as a fixed kernel
  * sequence with a device-side stopping flag (eq. admmStop, float64 norms); kernels after
- * convergence are no-ops, so the state on exit is the state at the stopping iteration. */
+ * convergence are no-ops, so the state on exit is the state at the stopping iteration.
+ * With a fixed rho in split-bfloat16 the z-step uses the per-slice operators described at
+ * epi_smooth_solve (built at the start of the solve when rho changed). */
 epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
                           const epi_admm_opts* opts, epi_admm_report* rep);
 
