@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define EPI_ABI_VERSION 4
+#define EPI_ABI_VERSION 5
 
 typedef enum {
   EPI_OK = 0,
@@ -124,24 +124,32 @@ enum { EPI_RHO_FIXED = 0, EPI_RHO_ADAPT = 1, EPI_RHO_ADAPT_FLOOR = 2 };
  * sqp_iters 1 (linearisations per b-step), check_every 8 (iterations between host polls
  * of the device-side stopping flag; results do not depend on it), rho 1e3,
  * eps_abs = eps_rel = 0.2 (eq. admmStop), rho_mode EPI_RHO_FIXED, tau 1.3, mu 10,
- * rho_min 1e2. */
+ * rho_min 1e2, qp_max_iter 0 (the cap on active-set iterations of one line's QP, eq. qp;
+ * 0 means 4 (M + 1)), with_lagrangian 0 (1: record the augmented Lagrangian of eq. Lp at
+ * every iterate, which costs two objective evaluations and a dot product per iteration;
+ * epi_solve_admm and epi_profile_admm only). */
 typedef struct {
   int32_t max_iter, sqp_iters, check_every;
   double rho, eps_abs, eps_rel;
   int32_t rho_mode;
   double tau, mu, rho_min;
+  int32_t qp_max_iter, with_lagrangian;
 } epi_admm_opts;
 
 /* ADMM report. Host arrays of length max_iter owned by the caller (NULL allowed):
  * per-iteration primal residual |b - z|, dual residual rho v |z_k - z_k+1| and their
- * tolerances (eq. admmStop, newest iterates), and the rho each iteration used.
+ * tolerances (eq. admmStop, newest iterates), the rho each iteration used and, when
+ * opts.with_lagrangian is set, the augmented Lagrangian
+ * L_rho(b, z, y) = f(b) + g(z) + y'(b - z) + (rho v / 2)|b - z|^2 of eq. Lp at the
+ * iteration's result (y = rho v u, f = D + (alpha v / 2)|D1 b|^2 on the feasible set,
+ * g = (alpha v / 2)(|D2 z|^2 + |D3 z|^2); left untouched otherwise).
  * max_active = largest number of active constraints of one PE line at exit of any
  * b-step; hard_lines = total count of (iteration, line) pairs that needed more than the
  * unconstrained step. */
 typedef struct {
   int32_t iters, converged, status, max_active;
   int64_t hard_lines;
-  double *r_pri, *r_dual, *eps_pri, *eps_dual, *rho;
+  double *r_pri, *r_dual, *eps_pri, *eps_dual, *rho, *lagrangian;
 } epi_admm_report;
 
 /* Kernel families of one ADMM iteration, for epi_profile_admm. */
@@ -156,10 +164,17 @@ enum {
 };
 
 /* Per-kernel-family device time of a profiled ADMM solve (milliseconds, HIP events on
- * the library's stream around every launch) and the number of launches. */
+ * the library's stream around every launch) and the number of launches. The pair of
+ * events around each launch adds the launch latency to every interval, so the profile also
+ * carries a back-to-back figure: after the solve, each family is launched isolated_reps
+ * times in a row (no event in between) on a copy of the final state, with the stopping
+ * test disabled, and us_isolated is the average device time per launch from one event
+ * pair around the whole run (0 for a family the problem does not have). */
 typedef struct {
   double ms[8];
   int64_t launches[8];
+  double us_isolated[8];
+  int32_t isolated_reps;
 } epi_kernel_profile;
 
 typedef struct epi_problem epi_problem;
@@ -290,7 +305,10 @@ epi_status epi_solve_multilevel_gnpcg(const epi_grid* grid, const float* d_Iplus
 /* The same solve as epi_solve_admm (same kernels in the same order, same results),
  * launched one kernel at a time without the captured graph, with a pair of HIP events
  * around every kernel on the library's stream. prof receives the device time per kernel
- * family. For measurement tools; slower than epi_solve_admm by the launch overhead. */
+ * family and, when prof->isolated_reps > 0 on entry, the back-to-back launch times
+ * described at epi_kernel_profile (the caller's arrays are not touched by that part; it
+ * works on the handle's GN work vectors). For measurement tools; slower than
+ * epi_solve_admm by the launch overhead. */
 epi_status epi_profile_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
                             const epi_admm_opts* opts, epi_admm_report* rep,
                             epi_kernel_profile* prof);
@@ -322,7 +340,8 @@ int64_t epi_batch_footprint(const epi_grid* grid, int32_t max_iter);
  * engine's), the image pair (N floats each, canonical layout), and its ADMM state arrays
  * d_b, d_z, d_u (n floats each, caller-owned, read and written in place until the slot
  * is released; |D1 b| <= 1 required, else EPI_EINFEASIBLE). opts: rho, eps_abs, eps_rel,
- * max_iter as for epi_solve_admm (sqp_iters must be 1; check_every is not used). On
+ * max_iter, rho_mode (with tau, mu, rho_min) and qp_max_iter as for epi_solve_admm
+ * (sqp_iters must be 1 and with_lagrangian 0; check_every is not used). On
  * success *slot is the slot index. EPI_EBUSY: no free slot or not enough budget. */
 epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const float* d_Iplus,
                            const float* d_Iminus, float* d_b, float* d_z, float* d_u,
@@ -330,19 +349,75 @@ epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const float* d_I
 
 /* Run iters_per_step ADMM iterations of every running volume (one graph replay; volumes
  * admitted since the last call join here), synchronise, and report in *running how many
- * volumes are still iterating. */
+ * volumes are still iterating. The graph is captured again only when the running set
+ * needs a kernel class or launch width the captured graph lacks, or when a class's work
+ * falls below half of its captured width (surplus workgroups return at once). */
 epi_status epi_batch_step(epi_batch* bt, int32_t* running);
 
 /* *finished = 1 once the slot's volume has converged or reached max_iter; then rep (may
  * be NULL) receives the report and histories as from epi_solve_admm. */
 epi_status epi_batch_poll(epi_batch* bt, int32_t slot, int32_t* finished, epi_admm_report* rep);
 
-/* Free a slot (finished or not): its workspace is released and its footprint leaves the
- * budget. The caller's arrays are not touched. */
+/* Free a slot (finished or not): its footprint leaves the budget and its workspace goes
+ * to the engine's cache of at most max_slots workspaces (the oldest cached one is freed
+ * when the cache is full). A later admission takes the smallest cached workspace that is
+ * large enough, keeping its DCT tables when the transverse grid matches and its per-slice
+ * operators when grid, alpha and rho match, so requests of recurring sizes are admitted
+ * without device allocation. The caller's arrays are not touched. */
 epi_status epi_batch_release(epi_batch* bt, int32_t slot);
+
+/* Counters of the engine since creation: admissions, admissions that had to allocate a
+ * new workspace, and captures of the iteration graph (one per change of the set of kernel
+ * classes or launch widths that the captured graph cannot cover). */
+epi_status epi_batch_stats(const epi_batch* bt, int64_t* admissions,
+                           int64_t* admissions_allocating, int64_t* graph_captures);
 
 /* Destroy the engine and every slot's workspace (NULL is a no-op). */
 void epi_batch_destroy(epi_batch* bt);
+
+/* ------------------------------------------------------------------------------------
+ * Request loop of the served solver: a FIFO of requests in front of one engine. The
+ * caller submits each request when it arrives (with its arrival time on
+ * epi_server_clock()) and calls epi_server_progress repeatedly; finished requests are
+ * collected with epi_server_take. Results are those of the engine (epi_batch_*), so a
+ * request's result does not depend on what else is in flight.
+ * ------------------------------------------------------------------------------------ */
+typedef struct epi_server epi_server;
+
+/* Seconds on the monotonic clock the server stamps admissions and completions with. */
+double epi_server_clock(void);
+
+/* Create a server around a new engine (arguments as for epi_batch_create). */
+epi_status epi_server_create(int32_t max_slots, int64_t hbm_budget_bytes, int32_t precision,
+                             int32_t iters_per_step, void* stream, epi_server** out);
+
+/* Queue one request (arguments as for epi_batch_admit; the caller's arrays must stay
+ * valid until the request has been taken). request_id is the caller's tag; arrival_s its
+ * arrival time on epi_server_clock(). Never EPI_EBUSY: the request waits in the queue. */
+epi_status epi_server_submit(epi_server* sv, int64_t request_id, double arrival_s,
+                             const epi_grid* grid, const float* d_Iplus, const float* d_Iminus,
+                             float* d_b, float* d_z, float* d_u, const epi_admm_opts* opts);
+
+/* Admit queued requests in arrival order while a slot and HBM budget are free, run one
+ * engine step (iters_per_step ADMM iterations of every running volume) if anything is
+ * running, move finished volumes to the completed list (releasing their slots) and admit
+ * again. Reports the number of queued, running and completed-but-not-taken requests (any
+ * pointer may be NULL). A request the engine rejects (EPI_EINFEASIBLE, EPI_EINVAL)
+ * completes at once with that status; a request that cannot fit even into an idle engine
+ * makes this call fail with EPI_ENOMEM. */
+epi_status epi_server_progress(epi_server* sv, int32_t* queued, int32_t* running,
+                               int32_t* ready);
+
+/* Take the oldest completed request: its tag, its latency (completion minus arrival,
+ * seconds) and, if rep is not NULL, its report as epi_batch_poll gives it (arrays of the
+ * request's max_iter entries, caller-owned, each may be NULL; lagrangian is not used).
+ * EPI_EBUSY when no request has completed. */
+epi_status epi_server_take(epi_server* sv, int64_t* request_id, double* latency_s,
+                           epi_admm_report* rep);
+
+/* Destroy the server and its engine (NULL is a no-op). Requests still queued or running
+ * are dropped; their arrays are not touched. */
+void epi_server_destroy(epi_server* sv);
 
 /* Release the handle and its workspace (NULL is a no-op). */
 void epi_destroy(epi_problem* p);

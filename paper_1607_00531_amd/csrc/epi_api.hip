@@ -89,7 +89,7 @@ struct epi_problem {
   // captured ADMM chunk
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
-  int g_chunk = 0, g_sqp = 0;
+  int g_chunk = 0, g_sqp = 0, g_lagr = 0;
   float *g_b = nullptr, *g_z = nullptr, *g_u = nullptr;
   bool g_zop = false;
   // per-kernel event timing (epi_profile_admm)
@@ -170,6 +170,8 @@ EPI_API void epi_admm_default_opts(epi_admm_opts* o) {
   o->rho_min = 1e2;
   o->eps_abs = 0.2;
   o->eps_rel = 0.2;
+  o->qp_max_iter = 0;
+  o->with_lagrangian = 0;
 }
 
 // ------------------------------------------------------------------------------------
@@ -444,6 +446,8 @@ static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float*
   p->hard_blocks = p->L < 128 ? p->L : 128;
   size_t cap = (size_t)lb * NQ_EVAL;
   cap = std::max(cap, (size_t)2048 * 2);
+  // the augmented-Lagrangian monitor: two objective evaluations and one dot product
+  cap = std::max(cap, (size_t)2 * lb * NQ_EVAL + (size_t)flat_blocks(p->n));
   cap = std::max(cap, (size_t)std::max(dct_tiles_axis2(p), dct_tiles_axis3(p)) * 4);
   p->partial_cap = cap;
   HIPCHK(hipMalloc(&p->partial, cap * sizeof(double)));
@@ -711,7 +715,37 @@ EPI_API epi_status epi_smooth_solve(epi_problem* p, const float* d_w, double rho
 // ------------------------------------------------------------------------------------
 // ADMM (Section 4.2)
 // ------------------------------------------------------------------------------------
-static epi_status admm_iteration(epi_problem* p, float* b, float* z, float* u, int sqp) {
+// The augmented Lagrangian (eq. Lp) at the iterate just finished: D and |D1 b|^2 from an
+// objective evaluation of b, |D2 z|^2 + |D3 z|^2 from one of z, u'(b - z) from a dot
+// product; the finalisation adds the rho terms from the history row of that iteration.
+static epi_status admm_lagrangian(epi_problem* p, const float* b, const float* z, const float* u) {
+  const int lb = line_blocks(p->la);
+  double* p1 = p->partial;
+  double* p2 = p1 + (size_t)lb * NQ_EVAL;
+  double* p3 = p2 + (size_t)lb * NQ_EVAL;
+  launch_eval(p->exec, p->P, 0, p->la, b, nullptr, 0, 0, nullptr, nullptr, nullptr, p1, p->st);
+  launch_eval(p->exec, p->P, 0, p->la, z, nullptr, 0, 0, nullptr, nullptr, nullptr, p2, p->st);
+  launch_udot(p->exec, p->n, u, b, z, p3);
+  CHKLAUNCH();
+  FinArgs f{};
+  f.kind = FIN_LAGRANGIAN;
+  f.partial = p1;
+  f.nb1 = lb;
+  f.partial2 = p2;
+  f.nb2 = lb;
+  f.partial3 = p3;
+  f.nb3 = flat_blocks(p->n);
+  f.v = p->v;
+  f.alpha = p->grid.alpha;
+  f.hist = p->hist;
+  f.hist_len = p->hist_cap;
+  launch_finalize(p->exec, f, p->st);
+  CHKLAUNCH();
+  return EPI_OK;
+}
+
+static epi_status admm_iteration(epi_problem* p, float* b, float* z, float* u, int sqp,
+                                 int lagr) {
   const int lb = line_blocks(p->la);
   for (int s = 0; s < sqp; ++s) {
     if (s > 0) {
@@ -735,6 +769,7 @@ static epi_status admm_iteration(epi_problem* p, float* b, float* z, float* u, i
   launch_finalize(p->exec, f, p->st);
   prof_end(p);
   CHKLAUNCH();
+  if (lagr) return admm_lagrangian(p, b, z, u);
   return EPI_OK;
 }
 
@@ -773,8 +808,9 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
                                   const epi_admm_opts* opts, epi_admm_report* rep) {
   if (!p || !d_b || !d_z || !d_u || !opts) return fail(EPI_EINVAL, "null argument");
   if (!(opts->rho > 0.0)) return fail(EPI_EINVAL, "rho must be > 0");
-  if (opts->max_iter < 0 || opts->sqp_iters < 1 || opts->check_every < 1)
-    return fail(EPI_EINVAL, "max_iter >= 0, sqp_iters >= 1, check_every >= 1 required");
+  if (opts->max_iter < 0 || opts->sqp_iters < 1 || opts->check_every < 1 || opts->qp_max_iter < 0)
+    return fail(EPI_EINVAL, "max_iter >= 0, sqp_iters >= 1, check_every >= 1, qp_max_iter >= 0 required");
+  const int lagr = opts->with_lagrangian ? 1 : 0;
   epi_status vo = validate_rho_opts(opts);
   if (vo != EPI_OK) return vo;
   enter(p);
@@ -802,6 +838,7 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
   h->v = p->v;
   h->admm_max = opts->max_iter;
   h->admm_done = opts->max_iter == 0 ? 2 : 0;
+  h->qp_max_iter = opts->qp_max_iter;
   init_rho_state(h, opts);
   HIPCHK(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->exec));
   s = prepare_zop(p, opts->rho, opts->rho_mode == EPI_RHO_FIXED);
@@ -810,11 +847,12 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
   const int chunk = opts->check_every;
   const bool use_graph = !p->prof_on;
   if (use_graph && (p->g_chunk != chunk || p->g_sqp != opts->sqp_iters || p->g_b != d_b ||
-                    p->g_z != d_z || p->g_u != d_u || p->g_zop != p->use_zop)) {
+                    p->g_z != d_z || p->g_u != d_u || p->g_zop != p->use_zop ||
+                    p->g_lagr != lagr)) {
     free_graph(p);
     HIPCHK(hipStreamBeginCapture(p->exec, hipStreamCaptureModeThreadLocal));
     for (int i = 0; i < chunk; ++i) {
-      s = admm_iteration(p, d_b, d_z, d_u, opts->sqp_iters);
+      s = admm_iteration(p, d_b, d_z, d_u, opts->sqp_iters, lagr);
       if (s != EPI_OK) {
         hipGraph_t tmp = nullptr;
         (void)hipStreamEndCapture(p->exec, &tmp);
@@ -830,6 +868,7 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
     p->g_z = d_z;
     p->g_u = d_u;
     p->g_zop = p->use_zop;
+    p->g_lagr = lagr;
   }
   int done = opts->max_iter == 0;
   int launched = 0;
@@ -838,7 +877,7 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
       HIPCHK(hipGraphLaunch(p->gexec, p->exec));
     } else {
       for (int i = 0; i < chunk; ++i) {
-        s = admm_iteration(p, d_b, d_z, d_u, opts->sqp_iters);
+        s = admm_iteration(p, d_b, d_z, d_u, opts->sqp_iters, lagr);
         if (s != EPI_OK) return s;
       }
     }
@@ -858,7 +897,7 @@ static epi_status solve_admm_impl(epi_problem* p, float* d_b, float* d_z, float*
     rep->hard_lines = h->hard_total;
     rep->status = h->numeric_bad ? EPI_ENUMERIC : EPI_OK;
     double* outs[EPI_HIST_ROWS] = {rep->r_pri, rep->r_dual, rep->eps_pri, rep->eps_dual,
-                                   rep->rho};
+                                   rep->rho, lagr ? rep->lagrangian : nullptr};
     for (int k = 0; k < EPI_HIST_ROWS; ++k)
       if (outs[k] && iters > 0)
         HIPCHK(hipMemcpy(outs[k], p->hist + (size_t)k * p->hist_cap, iters * sizeof(double),
@@ -876,6 +915,95 @@ EPI_API epi_status epi_solve_admm(epi_problem* p, float* d_b, float* d_z, float*
   return solve_admm_impl(p, d_b, d_z, d_u, opts, rep);
 }
 
+// Back-to-back launch times of each kernel family of an ADMM iteration: the final state
+// of the profiled solve is copied into the GN work vectors (x <- b, r <- z, zz <- u), the
+// device state is set so that no kernel stops early (stopping test off, no cap, history
+// writes past the end of the history), and every family runs `reps` times in a row
+// between one pair of events.
+static epi_status profile_isolated(epi_problem* p, const float* d_b, const float* d_z,
+                                   const float* d_u, int reps, epi_kernel_profile* prof) {
+  const size_t nb = (size_t)p->n * sizeof(float);
+  float *b = p->x, *z = p->r, *u = p->zz;
+  HIPCHK(hipMemcpyAsync(b, d_b, nb, hipMemcpyDeviceToDevice, p->exec));
+  HIPCHK(hipMemcpyAsync(z, d_z, nb, hipMemcpyDeviceToDevice, p->exec));
+  HIPCHK(hipMemcpyAsync(u, d_u, nb, hipMemcpyDeviceToDevice, p->exec));
+  HIPCHK(hipMemcpyAsync(p->st_h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
+  HIPCHK(hipStreamSynchronize(p->exec));
+  DevState* h = p->st_h;
+  h->admm_done = 0;
+  h->admm_max = 0x7fffffff;
+  h->admm_iter = p->hist_cap;     // admm_finalize writes history rows below hist_cap only
+  h->eps_abs = 0.0;
+  h->eps_rel = 0.0;
+  h->numeric_bad = 0;
+  h->rho_mode = 0;
+  h->u_scale = 1.0;
+  HIPCHK(hipMemcpyAsync(p->st, h, sizeof(DevState), hipMemcpyHostToDevice, p->exec));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int prec = p->grid.precision;
+  auto run = [&](int fam) {
+    for (int r = 0; r < reps; ++r) {
+      switch (fam) {
+        case EPI_K_BSTEP:
+        case EPI_K_BSTEP_HARD:
+          launch_admm_bstep_part(p->exec, fam == EPI_K_BSTEP ? 0 : 1, p->P, p->la, b, z, u,
+                                 p->w, p->hard_list, p->st, p->hard_blocks);
+          break;
+        case EPI_K_DCT_AXIS3: {
+          GemmArgs g = gemm_axis3(p, p->w, p->t1, false);
+          g.done = &p->st->admm_done;
+          launch_dct_axis3(p->exec, prec, g);
+        } break;
+        case EPI_K_DCT_AXIS2: {
+          GemmArgs g = gemm_axis2(p, p->t1, p->t2);
+          g.done = &p->st->admm_done;
+          launch_axis2(p, prec, g);
+        } break;
+        case EPI_K_DCT_LAST: {
+          GemmArgs g = p->m3 == 1 ? gemm_axis2(p, p->w, z) : gemm_axis3(p, p->t2, z, true);
+          g.done = &p->st->admm_done;
+          g.epi = 1;
+          g.b = b;
+          g.z = z;
+          g.u = u;
+          g.partial = p->partial_e;
+          if (p->m3 == 1) launch_axis2(p, prec, g);
+          else launch_dct_axis3(p->exec, prec, g);
+        } break;
+        default: {
+          FinArgs f{};
+          f.kind = FIN_ADMM;
+          f.partial = p->partial_e;
+          f.nb1 = zstep_epi_blocks(p);
+          f.hist = p->hist;
+          f.hist_len = p->hist_cap;
+          launch_finalize(p->exec, f, p->st);
+        } break;
+      }
+    }
+  };
+  epi_status out = EPI_OK;
+  for (int fam = 0; fam < EPI_K_COUNT && out == EPI_OK; ++fam) {
+    prof->us_isolated[fam] = 0.0;
+    if (p->m3 == 1 && (fam == EPI_K_DCT_AXIS3 || fam == EPI_K_DCT_AXIS2)) continue;
+    run(fam);   // warm-up of the family (code object, caches)
+    (void)hipEventRecord(e0, p->exec);
+    run(fam);
+    (void)hipEventRecord(e1, p->exec);
+    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      out = fail(EPI_EHIP, "isolated kernel timing");
+      break;
+    }
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) prof->us_isolated[fam] = 1e3 * ms / reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return out;
+}
+
 EPI_API epi_status epi_profile_admm(epi_problem* p, float* d_b, float* d_z, float* d_u,
                                     const epi_admm_opts* opts, epi_admm_report* rep,
                                     epi_kernel_profile* prof) {
@@ -886,11 +1014,18 @@ EPI_API epi_status epi_profile_admm(epi_problem* p, float* d_b, float* d_z, floa
     p->prof_ms[k] = 0.0;
     p->prof_cnt[k] = 0;
   }
+  const int reps = prof->isolated_reps;
   epi_status s = solve_admm_impl(p, d_b, d_z, d_u, opts, rep);
   p->prof_on = false;
   for (int k = 0; k < 8; ++k) {
     prof->ms[k] = p->prof_ms[k];
     prof->launches[k] = p->prof_cnt[k];
+    prof->us_isolated[k] = 0.0;
+  }
+  if (s == EPI_OK && reps > 0) {
+    enter(p);
+    s = profile_isolated(p, d_b, d_z, d_u, reps, prof);
+    leave(p);
   }
   return s;
 }

@@ -64,21 +64,22 @@ __global__ __launch_bounds__(256) void k_batch_bstep(BatchDev* bd, int cls) {
                                        &sbuf[wave][LinePad], lane, &st->numeric_bad);
   if (hard && lane == 0) {
     const int idx = atomicAdd(&bd->hard_count[cls], 1);
-    bd->hard_list[cls][idx] = HardItem{slot, line};
+    if (idx < total) bd->hard_list[cls][idx] = HardItem{slot, line};   // total entries
     atomicAdd(&st->hard_count, 1);
   }
 }
 
 template <int P>
 __global__ __launch_bounds__(64) void k_batch_hard(BatchDev* bd, int cls) {
-  const int nh = bd->hard_count[cls];
+  const RangeTable& T = bd->bt[cls];
+  const int nh = T.n ? min(bd->hard_count[cls], T.first[T.n]) : 0;
   if ((int)blockIdx.x >= nh) return;
   __shared__ HardLds<P> L;
   for (int h = blockIdx.x; h < nh; h += gridDim.x) {
     const HardItem it = bd->hard_list[cls][h];
     const BatchSlotDev& S = bd->slots[it.slot];
     hard_line_body<P>(S.la, (float)S.st->rho, (float)S.st->u_scale, S.b, S.z, S.u, S.w, it.line, L, threadIdx.x,
-                      &S.st->max_active);
+                      &S.st->max_active, S.st->qp_max_iter);
   }
 }
 
@@ -181,6 +182,36 @@ using namespace epi;
 
 namespace {
 
+// Device workspace of one resident volume. Released slots hand theirs to the engine's
+// cache, and admission takes a cached workspace whose buffers are large enough, so a
+// stream of requests of recurring sizes is admitted without device allocation: the DCT
+// tables are kept when the transverse grid matches, the per-slice operators when the
+// grid, alpha and rho match.
+struct Workspace {
+  float *w = nullptr, *t1 = nullptr, *t2 = nullptr;
+  double *partial = nullptr, *hist = nullptr;
+  size_t nb_cap = 0;      // bytes of w and t1 each
+  size_t t2_data = 0;     // bytes of t2 before the operator region
+  size_t zop_cap = 0;     // bytes of the operator region after t2_data
+  size_t part_cap = 0;    // doubles of partial
+  size_t hist_cap = 0;    // doubles of hist
+  DctTables tab;          // valid when tab_m2 > 0
+  int tab_m2 = 0, tab_m3 = 0, tab_prec = -1;
+  double tab_h2 = 0.0, tab_h3 = 0.0;
+  // operators in the region after t2_data, built for this grid and (alpha, rho)
+  int zop_m2 = 0, zop_m3 = 0;
+  double zop_h2 = 0.0, zop_h3 = 0.0, zop_alpha = 0.0, zop_rho = 0.0;
+  size_t bytes() const { return 2 * nb_cap + t2_data + zop_cap + 8 * (part_cap + hist_cap); }
+};
+
+static void free_workspace(Workspace& ws) {
+  void* bufs[] = {ws.w, ws.t1, ws.t2, ws.partial, ws.hist};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  free_dct_tables(&ws.tab);
+  ws = Workspace();
+}
+
 struct SlotHost {
   bool used = false, finished = false;
   epi_grid grid{};
@@ -188,6 +219,7 @@ struct SlotHost {
   long long n = 0, N = 0;
   const float *Ip = nullptr, *Im = nullptr;
   float *b = nullptr, *z = nullptr, *u = nullptr;
+  Workspace ws;
   float *w = nullptr, *t1 = nullptr, *t2 = nullptr;
   double* partial = nullptr;
   double* hist = nullptr;
@@ -208,7 +240,7 @@ int64_t workspace_bytes(const epi_grid* g, int max_iter) {
   // the split-bfloat16 per-slice operators of a fixed-rho volume (counted for every volume)
   const long long ce = (m2 + 1) / 2;
   const long long zop = (long long)zop_bytes((int)m2, (int)m3, 2 * (int)((ce + 15) / 16), (int)((ce + 31) / 32));
-  return 3 * n * 4 + part * 8 + 4LL * std::max(max_iter, 1) * 8 + tables + zop;
+  return 3 * n * 4 + part * 8 + (long long)EPI_HIST_ROWS * std::max(max_iter, 1) * 8 + tables + zop;
 }
 
 }  // namespace
@@ -225,6 +257,8 @@ struct BatchKey {
 
 struct epi_batch {
   int max_slots = 0, precision = 1, iters_per_step = 8;
+  std::vector<Workspace> cache;   // workspaces of released slots (at most max_slots)
+  long long admissions = 0, admissions_allocating = 0, captures = 0;
   int64_t budget = 0, used_bytes = 0;
   hipStream_t user = nullptr, exec = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -251,12 +285,99 @@ static void use_zop(const SlotHost& s, GemmArgs& g) {
   g.a_bstride = 2LL * s.tab.RT2 * s.tab.KS2 * 64;
 }
 
-static void batch_free_slot(SlotHost& s) {
-  void* bufs[] = {s.w, s.t1, s.t2, s.partial, s.hist};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
-  free_dct_tables(&s.tab);
+// Release a slot: its workspace goes to the cache (the least recently cached one is
+// freed when the cache is full), or is freed when `keep` is false.
+static void batch_free_slot(epi_batch* bt, SlotHost& s, bool keep = true) {
+  if (keep && s.ws.w) {
+    if ((int)bt->cache.size() >= bt->max_slots) {
+      free_workspace(bt->cache.front());
+      bt->cache.erase(bt->cache.begin());
+    }
+    bt->cache.push_back(s.ws);
+  } else {
+    free_workspace(s.ws);
+  }
   s = SlotHost();
+}
+
+// A workspace for slot s (sizes from s and the request): the smallest cached one that is
+// large enough, else a new allocation. Tables and operators are (re)built only when the
+// cached ones were made for another grid or another (alpha, rho).
+static epi_status take_workspace(epi_batch* bt, SlotHost& s, const epi_grid* grid,
+                                 const epi_admm_opts* opts) {
+  const size_t nb = (size_t)s.n * sizeof(float);
+  const size_t nb_al = (nb + 255) & ~(size_t)255;
+  const int ce2 = (s.m2 + 1) / 2;
+  const size_t zb = (bt->precision == EPI_PREC_MIXED && opts->rho_mode == EPI_RHO_FIXED && ce2 <= 128)
+                        ? zop_bytes(s.m2, s.m3, 2 * ((ce2 + 15) / 16), (ce2 + 31) / 32)
+                        : 0;
+  const long long tiles = std::max(tiles_axis3(s.M, s.m2), tiles_axis2(s.M, s.m3));
+  const size_t part = (size_t)std::max<long long>(tiles * NQ_ADMM_E, 4096);
+  const size_t hist = (size_t)EPI_HIST_ROWS * s.hist_len;
+  int best = -1;
+  for (int i = 0; i < (int)bt->cache.size(); ++i) {
+    const Workspace& c = bt->cache[i];
+    if (c.nb_cap >= nb && c.t2_data >= nb_al && c.zop_cap >= zb && c.part_cap >= part &&
+        c.hist_cap >= hist && (best < 0 || c.bytes() < bt->cache[best].bytes()))
+      best = i;
+  }
+  bt->admissions += 1;
+  Workspace& ws = s.ws;
+  if (best >= 0) {
+    ws = bt->cache[best];
+    bt->cache.erase(bt->cache.begin() + best);
+  } else {
+    bt->admissions_allocating += 1;
+    ws.nb_cap = nb;
+    ws.t2_data = nb_al;
+    ws.zop_cap = zb;
+    ws.part_cap = part;
+    ws.hist_cap = hist;
+    if (hipMalloc(&ws.w, nb) != hipSuccess || hipMalloc(&ws.t1, nb) != hipSuccess ||
+        hipMalloc(&ws.t2, nb_al + zb) != hipSuccess ||
+        hipMalloc(&ws.partial, part * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ws.hist, hist * sizeof(double)) != hipSuccess)
+      return fail(EPI_ENOMEM, "slot workspace");
+  }
+  const double h2 = grid->h[1], h3 = grid->h[2];
+  if (ws.tab_m2 != s.m2 || ws.tab_m3 != s.m3 || ws.tab_h2 != h2 || ws.tab_h3 != h3 ||
+      ws.tab_prec != bt->precision) {
+    free_dct_tables(&ws.tab);
+    ws.tab_m2 = 0;
+    epi_status ts = build_dct_tables(s.m2, s.m3, h2, h3, bt->precision, &ws.tab);
+    if (ts != EPI_OK) return ts;
+    ws.tab_m2 = s.m2;
+    ws.tab_m3 = s.m3;
+    ws.tab_h2 = h2;
+    ws.tab_h3 = h3;
+    ws.tab_prec = bt->precision;
+  }
+  s.w = ws.w;
+  s.t1 = ws.t1;
+  s.t2 = ws.t2;
+  s.partial = ws.partial;
+  s.hist = ws.hist;
+  s.tab = ws.tab;
+  s.zop = nullptr;
+  if (zb) {
+    s.zop = reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(ws.t2) + ws.t2_data);
+    if (ws.zop_m2 != s.m2 || ws.zop_m3 != s.m3 || ws.zop_h2 != h2 || ws.zop_h3 != h3 ||
+        ws.zop_alpha != grid->alpha || ws.zop_rho != opts->rho) {
+      ws.zop_m2 = 0;
+      if (hipMemsetAsync(s.zop, 0, zb, bt->exec) != hipSuccess ||
+          launch_build_zop(bt->exec, s.m2, s.m3, h2, h3, grid->alpha, opts->rho, s.tab.RT2,
+                           s.tab.KS2, s.zop) != 0 ||
+          hipGetLastError() != hipSuccess)
+        return fail(EPI_EHIP, "slot operator build");
+      ws.zop_m2 = s.m2;
+      ws.zop_m3 = s.m3;
+      ws.zop_h2 = h2;
+      ws.zop_h3 = h3;
+      ws.zop_alpha = grid->alpha;
+      ws.zop_rho = opts->rho;
+    }
+  }
+  return EPI_OK;
 }
 
 EPI_API int64_t epi_batch_footprint(const epi_grid* grid, int32_t max_iter) {
@@ -272,7 +393,8 @@ EPI_API void epi_batch_destroy(epi_batch* bt) {
   if (bt->gexec) (void)hipGraphExecDestroy(bt->gexec);
   if (bt->graph) (void)hipGraphDestroy(bt->graph);
   for (auto& s : bt->slots)
-    if (s.used) batch_free_slot(s);
+    if (s.used) batch_free_slot(bt, s, false);
+  for (auto& ws : bt->cache) free_workspace(ws);
   for (int c = 0; c <= EPI_PMAX; ++c)
     if (bt->hard[c]) (void)hipFree(bt->hard[c]);
   if (bt->d_bd) (void)hipFree(bt->d_bd);
@@ -352,8 +474,10 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
   *slot_out = -1;
   epi_status vs = validate_grid(grid);
   if (vs != EPI_OK) return vs;
-  if (!(opts->rho > 0.0) || opts->max_iter < 1 || opts->sqp_iters != 1)
-    return fail(EPI_EINVAL, "batched ADMM needs rho > 0, max_iter >= 1, sqp_iters = 1");
+  if (!(opts->rho > 0.0) || opts->max_iter < 1 || opts->sqp_iters != 1 || opts->qp_max_iter < 0)
+    return fail(EPI_EINVAL, "batched ADMM needs rho > 0, max_iter >= 1, sqp_iters = 1, qp_max_iter >= 0");
+  if (opts->with_lagrangian)
+    return fail(EPI_EINVAL, "the batched engine does not record the augmented Lagrangian");
   {
     epi_status vo = validate_rho_opts(opts);
     if (vo != EPI_OK) return vo;
@@ -389,36 +513,19 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
   s.footprint = fp;
   s.hist_len = opts->max_iter;
   s.used = true;   // from here on a failure releases the slot
-  auto undo = [&](epi_status st) {
-    batch_free_slot(s);
-    return st;
-  };
-  const size_t nb = (size_t)s.n * sizeof(float);
   // a fixed-rho split-bfloat16 volume takes its j-axis pass through per-slice operators (as
   // the single-volume solver does), kept behind t2
-  const size_t nb_al = (nb + 255) & ~(size_t)255;
-  const int ce2 = (s.m2 + 1) / 2;
-  const size_t zb = (bt->precision == EPI_PREC_MIXED && opts->rho_mode == EPI_RHO_FIXED && ce2 <= 128)
-                        ? zop_bytes(s.m2, s.m3, 2 * ((ce2 + 15) / 16), (ce2 + 31) / 32)
-                        : 0;
-  if (hipMalloc(&s.w, nb) != hipSuccess || hipMalloc(&s.t1, nb) != hipSuccess ||
-      hipMalloc(&s.t2, nb_al + zb) != hipSuccess)
-    return undo(fail(EPI_ENOMEM, "slot workspace"));
-  const long long tiles = std::max(tiles_axis3(s.M, s.m2), tiles_axis2(s.M, s.m3));
-  const size_t part = (size_t)std::max<long long>(tiles * NQ_ADMM_E, 4096);
-  if (hipMalloc(&s.partial, part * sizeof(double)) != hipSuccess ||
-      hipMalloc(&s.hist, (size_t)EPI_HIST_ROWS * s.hist_len * sizeof(double)) != hipSuccess)
-    return undo(fail(EPI_ENOMEM, "slot buffers"));
-  epi_status ts = build_dct_tables(s.m2, s.m3, grid->h[1], grid->h[2], bt->precision, &s.tab);
-  if (ts != EPI_OK) return undo(ts);
-  if (zb) {
-    s.zop = reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(s.t2) + nb_al);
-    if (hipMemsetAsync(s.zop, 0, zb, bt->exec) != hipSuccess ||
-        launch_build_zop(bt->exec, s.m2, s.m3, grid->h[1], grid->h[2], grid->alpha, opts->rho,
-                         s.tab.RT2, s.tab.KS2, s.zop) != 0 ||
-        hipGetLastError() != hipSuccess)
-      return undo(fail(EPI_EHIP, "slot operator build"));
+  {
+    epi_status ws = take_workspace(bt, s, grid, opts);
+    if (ws != EPI_OK) {
+      batch_free_slot(bt, s, false);   // possibly incomplete: not cached
+      return ws;
+    }
   }
+  auto undo = [&](epi_status st) {
+    batch_free_slot(bt, s);
+    return st;
+  };
   // feasibility of the starting field and the slot's stopping state
   batch_enter(bt);
   DevState* dst = bt->d_st + sid;
@@ -446,6 +553,7 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
   hst->sqrt_n = sqrt((double)s.n);
   hst->v = grid->h[0] * grid->h[1] * grid->h[2];
   hst->admm_max = opts->max_iter;
+  hst->qp_max_iter = opts->qp_max_iter;
   init_rho_state(hst, opts);
   if (hipMemcpy(dst, hst, sizeof(DevState), hipMemcpyHostToDevice) != hipSuccess)
     return undo(fail(EPI_EHIP, "state init"));
@@ -534,6 +642,19 @@ static epi_status batch_rebuild(epi_batch* bt, BatchKey* key) {
   return EPI_OK;
 }
 
+// The captured graph can run the work of `key` when every class present in key has at most
+// the captured launch width and at least half of it (spare workgroups return at once; the
+// bound keeps their share small). Volumes leaving the batch then cost no new capture.
+static bool key_fits(const BatchKey& key, const BatchKey& captured, hipGraphExec_t gexec) {
+  if (!gexec) return false;
+  auto fits = [](int k, int c) { return k == 0 || (c >= k && 2 * k >= c); };
+  for (int c = 0; c <= EPI_PMAX; ++c)
+    if (!fits(key.bstep[c], captured.bstep[c])) return false;
+  for (int c = 0; c < 8; ++c)
+    if (!fits(key.dct[c], captured.dct[c])) return false;
+  return true;
+}
+
 static void batch_iteration(epi_batch* bt, const BatchKey& key) {
   hipStream_t s = bt->exec;
   BatchDev* bd = bt->d_bd;
@@ -585,7 +706,7 @@ EPI_API epi_status epi_batch_step(epi_batch* bt, int32_t* running) {
     epi_status s = batch_rebuild(bt, &key);
     if (s != EPI_OK) return s;
     bt->dirty = false;
-    if (key != bt->graph_key && bt->running > 0) {
+    if (key != bt->graph_key && bt->running > 0 && !key_fits(key, bt->graph_key, bt->gexec)) {
       if (bt->gexec) BHIPCHK(hipGraphExecDestroy(bt->gexec));
       if (bt->graph) BHIPCHK(hipGraphDestroy(bt->graph));
       bt->gexec = nullptr;
@@ -598,6 +719,7 @@ EPI_API epi_status epi_batch_step(epi_batch* bt, int32_t* running) {
         return fail(EPI_EHIP, "graph capture: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
       BHIPCHK(hipGraphInstantiate(&bt->gexec, bt->graph, nullptr, nullptr, 0));
       bt->graph_key = key;
+      bt->captures += 1;
     }
   }
   if (bt->running > 0) {
@@ -634,11 +756,21 @@ EPI_API epi_status epi_batch_poll(epi_batch* bt, int32_t slot, int32_t* finished
   rep->max_active = h.max_active;
   rep->hard_lines = h.hard_total;
   rep->status = h.numeric_bad ? EPI_ENUMERIC : EPI_OK;
-  double* outs[EPI_HIST_ROWS] = {rep->r_pri, rep->r_dual, rep->eps_pri, rep->eps_dual, rep->rho};
-  for (int k = 0; k < EPI_HIST_ROWS; ++k)
+  double* outs[EPI_HIST_ROWS - 1] = {rep->r_pri, rep->r_dual, rep->eps_pri, rep->eps_dual, rep->rho};
+  for (int k = 0; k < EPI_HIST_ROWS - 1; ++k)
     if (outs[k] && iters > 0)
       BHIPCHK(hipMemcpy(outs[k], s.hist + (size_t)k * s.hist_len,
                         std::min(iters, s.hist_len) * sizeof(double), hipMemcpyDeviceToHost));
+  return EPI_OK;
+}
+
+EPI_API epi_status epi_batch_stats(const epi_batch* bt, int64_t* admissions,
+                                   int64_t* admissions_allocating, int64_t* graph_captures) {
+  if (!bt || !admissions || !admissions_allocating || !graph_captures)
+    return fail(EPI_EINVAL, "null argument");
+  *admissions = bt->admissions;
+  *admissions_allocating = bt->admissions_allocating;
+  *graph_captures = bt->captures;
   return EPI_OK;
 }
 
@@ -649,7 +781,7 @@ EPI_API epi_status epi_batch_release(epi_batch* bt, int32_t slot) {
   BHIPCHK(hipStreamSynchronize(bt->exec));
   SlotHost& s = bt->slots[slot];   // a running volume may be released (cancelled)
   bt->used_bytes -= s.footprint;
-  batch_free_slot(s);
+  batch_free_slot(bt, s);
   bt->dirty = true;
   return EPI_OK;
 }

@@ -45,6 +45,9 @@ struct DevState {
   // next iteration has read it (the rescale rho_old / rho_new of the scaled dual)
   double u_scale, tau, mu, rho_min;
   int rho_mode, pad5;
+  // active-set iteration cap of one line's QP (0: 4 (M + 1)); the last iteration whose
+  // augmented Lagrangian was recorded (with_lagrangian)
+  int qp_max_iter, lagr_last;
   // corrected-image pair: sum a, sum b, sum a^2, sum b^2, sum ab, sum (a - b)^2
   double quality[6];
 };

@@ -385,6 +385,97 @@ __device__ __forceinline__ void wave_tridiag_solve(const float (&d)[P], const fl
   for (int j = 0; j < P; ++j) r[j] = R[j] - A[j] * Xp - C[j] * X;
 }
 
+// The same solve split into a factorisation of the matrix and any number of solves with
+// it (the b-step solves twice with one matrix: the step and its refinement). The
+// factorisation keeps, per lane, the pivots' reciprocals and the Thomas multipliers of its
+// block, the block's coupling coefficients A, C to the neighbouring lanes' last unknowns,
+// and the multipliers of the six cyclic-reduction steps; a solve then only sweeps the
+// right-hand side through them (twelve shuffles instead of forty-eight).
+template <int P>
+struct WaveTriFactor {
+  float inv[P], cp[P], A[P], e[P];   // C (below) is rebuilt from cp by each solve
+  float al[6], ga[6];
+  float ibf;
+};
+
+template <int P>
+__device__ __forceinline__ void wave_tridiag_factor(const float (&d)[P], const float (&e)[P],
+                                                    WaveTriFactor<P>& F, int lane) {
+  float ap[P];
+  const float a0 = shfl_up0(e[P - 1], 1, lane);
+  F.inv[0] = rcp_f(d[0]);
+  ap[0] = a0 * F.inv[0];
+  F.cp[0] = e[0] * F.inv[0];
+#pragma unroll
+  for (int j = 1; j < P; ++j) {
+    const float a = e[j - 1];
+    F.inv[j] = rcp_f(d[j] - a * F.cp[j - 1]);
+    ap[j] = -a * ap[j - 1] * F.inv[j];
+    F.cp[j] = e[j] * F.inv[j];
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) F.e[j] = e[j];
+  float C[P];
+  F.A[P - 1] = 0.0f;
+  C[P - 1] = -1.0f;
+#pragma unroll
+  for (int j = P - 2; j >= 0; --j) {
+    F.A[j] = ap[j] - F.cp[j] * F.A[j + 1];
+    C[j] = -F.cp[j] * C[j + 1];
+  }
+  const float An = shfl_down0(F.A[0], 1, lane);
+  const float Cn = shfl_down0(C[0], 1, lane);
+  const float cpl = F.cp[P - 1];
+  float ra = (lane == 0) ? 0.0f : ap[P - 1];
+  float rb = 1.0f - cpl * An;
+  float rc = (lane == 63) ? 0.0f : -cpl * Cn;
+  int q = 0;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1, ++q) {
+    const float ib = rcp_f(rb);
+    const float am = __shfl_up(ra, s, 64), ibm = __shfl_up(ib, s, 64), cm = __shfl_up(rc, s, 64);
+    const float aq = __shfl_down(ra, s, 64), ibq = __shfl_down(ib, s, 64), cq = __shfl_down(rc, s, 64);
+    const float al = -ra * ibm, ga = -rc * ibq;
+    F.al[q] = al;
+    F.ga[q] = ga;
+    const float na = al * am, nc = ga * cq;
+    rb = rb + al * cm + ga * aq;
+    ra = na;
+    rc = nc;
+  }
+  F.ibf = rcp_f(rb);
+}
+
+// r <- M^{-1} r with the factorisation F (same arithmetic as wave_tridiag_solve).
+template <int P>
+__device__ __forceinline__ void wave_tridiag_apply(const WaveTriFactor<P>& F, float (&r)[P],
+                                                   int lane) {
+  float rp[P];
+  rp[0] = r[0] * F.inv[0];
+#pragma unroll
+  for (int j = 1; j < P; ++j) rp[j] = (r[j] - F.e[j - 1] * rp[j - 1]) * F.inv[j];
+  float R[P];
+  R[P - 1] = 0.0f;
+#pragma unroll
+  for (int j = P - 2; j >= 0; --j) R[j] = rp[j] - F.cp[j] * R[j + 1];
+  const float Rn = shfl_down0(R[0], 1, lane);
+  float rr = rp[P - 1] - F.cp[P - 1] * Rn;
+  int q = 0;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1, ++q) {
+    const float xm = __shfl_up(rr, s, 64), xq = __shfl_down(rr, s, 64);
+    rr = rr + F.al[q] * xm + F.ga[q] * xq;
+  }
+  const float X = rr * F.ibf;
+  const float Xp = shfl_up0(X, 1, lane);
+  float C = -1.0f;
+#pragma unroll
+  for (int j = P - 1; j >= 0; --j) {
+    if (j < P - 1) C = -F.cp[j] * C;
+    r[j] = R[j] - F.A[j] * Xp - C * X;
+  }
+}
+
 // ------------------------------------------------------------------------------------
 // Penalty phi (eq. P) and its derivatives (eq. dphi), |x| < 1
 // ------------------------------------------------------------------------------------

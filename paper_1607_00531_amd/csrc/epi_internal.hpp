@@ -29,8 +29,9 @@ GemmArgs make_gemm_axis2(int M, int m2, int m3, float alpha, const DctTables& t,
 int tiles_axis3(int M, int m2);
 int tiles_axis2(int M, int m3);
 
-// Rows of the device-side ADMM history: r_pri, r_dual, eps_pri, eps_dual, rho.
-constexpr int EPI_HIST_ROWS = 5;
+// Rows of the device-side ADMM history: r_pri, r_dual, eps_pri, eps_dual, rho, and the
+// augmented Lagrangian (filled only by solves that ask for it).
+constexpr int EPI_HIST_ROWS = 6;
 epi_status validate_rho_opts(const epi_admm_opts* opts);
 void init_rho_state(DevState* h, const epi_admm_opts* opts);
 

@@ -42,6 +42,10 @@ void launch_precond(hipStream_t s, int P, LineArgs a, int precond, const float* 
 // symmetric Gauss-Seidel z = P_SGS^-1 r (all levels of both sweeps; z may not alias r)
 void launch_sgs(hipStream_t s, int P, LineArgs a, const float* hdiag, const float* hoff,
                 const float* r, float* z, const DevState* st, int gate);
+// part 0: the fast-path kernel over all lines; part 1: the active-set kernel
+void launch_admm_bstep_part(hipStream_t s, int part, int P, LineArgs a, float* b,
+                            const float* z, const float* u, float* w, int* hard_list,
+                            DevState* st, int hard_blocks);
 void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* z,
                        const float* u, float* w, int* hard_list, DevState* st, int hard_blocks,
                        const std::function<void(int)>& before,
@@ -56,6 +60,9 @@ void launch_matvec(hipStream_t s, int P, LineArgs a, const float* z, const float
                    float* pnew, const float* hdiag, const float* hoff, float* q, double* partial,
                    const DevState* st);
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial);
+// partial sums of u'(b - z) (the multiplier term of the augmented Lagrangian)
+void launch_udot(hipStream_t s, long long n, const float* u, const float* b, const float* z,
+                 double* partial);
 void launch_sgs_finish(hipStream_t s, long long n, const float* r, const float* z, float* p,
                        double* partial, int first, const DevState* st);
 void launch_gn_step(hipStream_t s, long long n, float* b, const float* d, double* partial,
@@ -76,7 +83,8 @@ enum FinKind : int {
   FIN_ADMM = 7,        // residuals, tolerances, stopping flag, history
   FIN_LS_INIT = 8,     // J0 = value; clear the line-search state
   FIN_HARD_RESET = 9,  // fold hard_count into hard_total between SQP linearisations
-  FIN_QUALITY = 10     // -> st->quality (sums of the corrected-image pair)
+  FIN_QUALITY = 10,    // -> st->quality (sums of the corrected-image pair)
+  FIN_LAGRANGIAN = 11  // augmented Lagrangian of the last ADMM iterate -> history row 5
 };
 struct FinArgs {
   int kind;

@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
                                        &st->numeric_bad);
   if (valid && hard && lane == 0) {
     const int idx = atomicAdd(&st->hard_count, 1);
-    hard_list[idx] = line;
+    if (idx < a.L) hard_list[idx] = line;   // hard_list holds L entries
   }
 }
 
@@ -473,12 +473,12 @@ __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __res
                                                         float* __restrict__ wvec,
                                                         const int* hard_list, DevState* st) {
   if (st->admm_done) return;
-  const int nhard = st->hard_count;
+  const int nhard = min(st->hard_count, a.L);
   if ((int)blockIdx.x >= nhard) return;
   __shared__ HardLds<P> L;
   for (int h = blockIdx.x; h < nhard; h += gridDim.x)
     hard_line_body<P>(a, (float)st->rho, (float)st->u_scale, bvec, zvec, uvec, wvec, hard_list[h], L, threadIdx.x,
-                      &st->max_active);
+                      &st->max_active, st->qp_max_iter);
 }
 
 // ------------------------------------------------------------------------------------
@@ -553,19 +553,28 @@ void launch_sgs(hipStream_t s, int P, LineArgs a, const float* hdiag, const floa
   }
 }
 
+void launch_admm_bstep_part(hipStream_t s, int part, int P, LineArgs a, float* b,
+                            const float* z, const float* u, float* w, int* hard_list,
+                            DevState* st, int hard_blocks) {
+  if (part == 0) {
+    const int nb = line_blocks(a);
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep<PP>), dim3(nb), dim3(256), 0, s, a, b,
+                                         z, u, w, hard_list, st));
+  } else {
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep_hard<PP>), dim3(hard_blocks), dim3(64),
+                                         0, s, a, b, z, u, w, hard_list, st));
+  }
+}
+
 void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* z,
                        const float* u, float* w, int* hard_list, DevState* st, int hard_blocks,
                        const std::function<void(int)>& before,
                        const std::function<void()>& after) {
-  const int nb = line_blocks(a);
-  before(0);
-  EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep<PP>), dim3(nb), dim3(256), 0, s, a, b, z,
-                                       u, w, hard_list, st));
-  after();
-  before(1);
-  EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep_hard<PP>), dim3(hard_blocks), dim3(64), 0,
-                                       s, a, b, z, u, w, hard_list, st));
-  after();
+  for (int part = 0; part < 2; ++part) {
+    before(part);
+    launch_admm_bstep_part(s, part, P, a, b, z, u, w, hard_list, st, hard_blocks);
+    after();
+  }
 }
 
 }  // namespace epi

@@ -129,8 +129,7 @@ __device__ __forceinline__ void qp_data(const LineArgs& a, float rho, const floa
                                         const float (&z)[P], const float (&u)[P],
                                         const float* sIp, const float* sIm, int lane,
                                         float (&Gd)[P], float (&Go)[P], float (&c)[P],
-                                        float (&g)[P]) {
-  Cells<P> C;
+                                        float (&g)[P], Cells<P>& C) {
   eval_cells<P, PADDED>(a, b, sIp, sIm, lane, C);
   float Jrr[P], rpJ[P], gprev[P], JrPrev[P];
 #pragma unroll
@@ -155,6 +154,86 @@ __device__ __forceinline__ void qp_data(const LineArgs& a, float rho, const floa
     Gd[j] = in ? gd : 1.0f;
     Go[j] = (i < a.M) ? a.v * C.Jl[j] * C.Jr[j] - qa : 0.0f;
   }
+}
+
+// G x of the b-step QP in the structured form v J'(J x) + alpha v D1'(D1 x) + rho v x,
+// from the per-cell Jacobian entries (C.Jl, C.Jr, zero past the line) and short
+// differences of x. For fields that are smooth along the line the diagonal/off-diagonal
+// form of G cancels: its diagonal 2 alpha v / h^2 + rho v is rounded to float32 relative
+// to alpha v / h^2 (about 1e4 times rho v at 240 faces per line), which perturbs the
+// smallest eigenvalues of G, and with them the step, by about 1e-3 relative. Here the
+// difference (x_{c+1} - x_c) is formed first, so a constant x gives exactly v J'J x + rho v x.
+template <int P>
+__device__ __forceinline__ void qp_apply(const LineArgs& a, float rho, const Cells<P>& C,
+                                         const float (&x)[P], float (&y)[P], int lane) {
+  const float xnext = shfl_down0(x[0], 1, lane);
+  float t[P], jx[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const float xr = (j < P - 1) ? x[j + 1] : xnext;
+    const bool in = P * lane + j < a.M;
+    t[j] = in ? (xr - x[j]) * a.inv_hp : 0.0f;       // D1 x (cell)
+    jx[j] = C.Jl[j] * x[j] + C.Jr[j] * xr;           // J x (cell; Jl = Jr = 0 past the line)
+  }
+  float tprev[P], jxprev[P], jrprev[P];
+  prev_cell<P>(t, tprev, lane);
+  prev_cell<P>(jx, jxprev, lane);
+  prev_cell<P>(C.Jr, jrprev, lane);
+  const float av = a.alpha * a.v, rv = rho * a.v;
+#pragma unroll
+  for (int j = 0; j < P; ++j)
+    y[j] = a.v * (C.Jl[j] * jx[j] + jrprev[j] * jxprev[j]) + av * (tprev[j] - t[j]) * a.inv_hp +
+           rv * x[j];
+}
+
+// x = G^{-1} rhs for the b-step QP of one line: the wave-parallel solve with G in
+// diagonal/off-diagonal form, then one step of iterative refinement whose residual
+// rhs - G x is formed with qp_apply. The first solve is accurate to about kappa(G) eps
+// relative to x (1e-3 on the smooth modes of long lines); the refined x to its square.
+// Padding slots (faces past the line) have rhs = 0 and the identity row. The Jacobian
+// entries and the right-hand side wait in three LDS line buffers of the caller's
+// (park[0..2], each thread its own slots) while the matrix is factorised, which keeps the
+// factorisation, the largest live set of the b-step, within the register budget of seven
+// wavefronts per SIMD.
+template <int P>
+__device__ __forceinline__ void qp_solve_refined(const LineArgs& a, float rho, const Cells<P>& C,
+                                                 const float (&Gd)[P], const float (&Go)[P],
+                                                 const float (&rhs)[P], float (&x)[P], int lane,
+                                                 float* const (&park)[3]) {
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int t = lds_pad(P * lane + j);
+    park[0][t] = C.Jl[j];
+    park[1][t] = C.Jr[j];
+    park[2][t] = rhs[j];
+  }
+  // the parked values are read back below, not forwarded in registers
+  asm volatile("" ::: "memory");
+  WaveTriFactor<P> F;
+  wave_tridiag_factor<P>(Gd, Go, F, lane);
+  Cells<P> J;
+  float b0[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int t = lds_pad(P * lane + j);
+    x[j] = park[2][t];
+  }
+  wave_tridiag_apply<P>(F, x, lane);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int t = lds_pad(P * lane + j);
+    J.Jl[j] = park[0][t];
+    J.Jr[j] = park[1][t];
+    b0[j] = park[2][t];
+  }
+  float gx[P], res[P];
+  qp_apply<P>(a, rho, J, x, gx, lane);
+  const int NF = a.M + 1;
+#pragma unroll
+  for (int j = 0; j < P; ++j) res[j] = (P * lane + j < NF) ? b0[j] - gx[j] : 0.0f;
+  wave_tridiag_apply<P>(F, res, lane);
+#pragma unroll
+  for (int j = 0; j < P; ++j) x[j] += res[j];
 }
 
 // Tolerances of the float32 active-set logic (relative to the unit bound on |D1 b|).
@@ -193,37 +272,43 @@ __device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho, fl
     u[j] = v[4][j] * us;   // pending rescale of the scaled dual (1 with a fixed rho)
   }
   float Gd[P], Go[P], c[P], g[P];
-  qp_data<P, true>(a, rho, b, z, u, sIp, sIm, lane, Gd, Go, c, g);
-  float x[P];
+  Cells<P> C;
+  qp_data<P, true>(a, rho, b, z, u, sIp, sIm, lane, Gd, Go, c, g, C);
+  float x[P], mc[P];
   bool hard = false;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    x[j] = -c[j];
+    mc[j] = -c[j];
     if (P * lane + j < a.M && fabsf(g[j]) >= 1.0f - EPI_TOL_ACTIVE) hard = true;
   }
-  wave_tridiag_solve<P>(Gd, Go, x, lane);
+  // the image lines and z are no longer needed: their buffers hold the parked values
+  float* const park[3] = {sIp, sIm, sw + 3 * LineBuf<P>::SIZE};
+  qp_solve_refined<P>(a, rho, C, Gd, Go, mc, x, lane, park);
+  // b and u are read again from their staged LDS lines (unchanged since staging) rather
+  // than kept in registers across the two solves; g = D1 b is formed as in eval_cells.
+  const float* sb = sw + 2 * LineBuf<P>::SIZE;
+  const float* su = sw + 4 * LineBuf<P>::SIZE;
   const float xnext = shfl_down0(x[0], 1, lane);
   bool bad = false;
+  float ov[2][P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int cidx = P * lane + j;
+    const float bj = sb[lds_pad(cidx)];
     if (cidx < a.M) {
       const float xr = (j < P - 1) ? x[j + 1] : xnext;
-      const float gn = g[j] + (xr - x[j]) * a.inv_hp;
+      const float gj = (sb[lds_pad(cidx + 1)] - bj) * a.inv_hp;
+      const float gn = gj + (xr - x[j]) * a.inv_hp;
       if (!(fabsf(gn) <= 1.0f)) hard = true;   // also catches NaN
     }
     if (cidx < NF && !(fabsf(x[j]) < 3.0e38f)) bad = true;
+    ov[0][j] = bj + x[j];
+    ov[1][j] = ov[0][j] + su[lds_pad(cidx)] * us;
   }
   hard = __any(hard);
   if (bad && valid && lane == 0) atomicAdd(numeric_bad, 1);
   const bool wr = valid && !hard;
   float* outs[2] = {bvec + base, wvec + base};
-  float ov[2][P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    ov[0][j] = b[j] + x[j];
-    ov[1][j] = ov[0][j] + u[j];
-  }
   stage_out_n<P, 2>(outs, NF, wr, sw + 2 * LineBuf<P>::SIZE, ov, lane);
   return hard;
 }
@@ -367,7 +452,8 @@ __device__ __forceinline__ void hard_line_body(const LineArgs& a, float rho, flo
                                                const float* __restrict__ zvec,
                                                const float* __restrict__ uvec,
                                                float* __restrict__ wvec, int line,
-                                               HardLds<P>& L, int lane, int* max_active) {
+                                               HardLds<P>& L, int lane, int* max_active,
+                                               int qp_max) {
   const int NF = a.M + 1;
   const size_t base = (size_t)line * NF;
   for (int t = lane; t < 64 * P; t += 64) {
@@ -381,7 +467,8 @@ __device__ __forceinline__ void hard_line_body(const LineArgs& a, float rho, flo
 #pragma unroll
   for (int j = 0; j < P; ++j) u[j] *= us;
   float Gdr[P], Gor[P], cr[P], gr[P];
-  qp_data<P>(a, rho, b, z, u, L.sIp, L.sIm, lane, Gdr, Gor, cr, gr);
+  Cells<P> C;
+  qp_data<P>(a, rho, b, z, u, L.sIp, L.sIm, lane, Gdr, Gor, cr, gr, C);
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int i = P * lane + j;
@@ -393,7 +480,7 @@ __device__ __forceinline__ void hard_line_body(const LineArgs& a, float rho, flo
   __syncthreads();
   if (lane == 0)
     L.res = active_set_serial(NF, a.hp, L.Gd, L.Go, L.cv, L.g0, L.x, L.p, L.o, L.q, L.rd, L.ro,
-                              L.rr, L.grp, L.stt, 4 * NF);
+                              L.rr, L.grp, L.stt, qp_max > 0 ? qp_max : 4 * NF);
   __syncthreads();
   float bn[P], wn[P];
 #pragma unroll

@@ -119,6 +119,17 @@ __global__ __launch_bounds__(256) void k_dot(long long n, const float* __restric
   block_partials<1>(acc, partial, blockIdx.x);
 }
 
+__global__ __launch_bounds__(256) void k_udot(long long n, const float* __restrict__ u,
+                                              const float* __restrict__ b,
+                                              const float* __restrict__ z, double* partial) {
+  long long lo, hi;
+  chunk_of(n, lo, hi);
+  double acc[1] = {0.0};
+  for (long long f = lo + threadIdx.x; f < hi; f += blockDim.x)
+    acc[0] += (double)u[f] * ((double)b[f] - (double)z[f]);
+  block_partials<1>(acc, partial, blockIdx.x);
+}
+
 // After a symmetric Gauss-Seidel application: the PCG partial sums with the new z, in the
 // order of the line kernel they replace (first = 1: r.z, r.r as at the PCG start, and
 // p = z; first = 0: r.r, r.z as in the update). gate: skip once the PCG has stopped.
@@ -294,6 +305,24 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f, DevState* st) {
       reduce_partials<NQ_QUALITY>(f.partial, f.nb1, s);
       if (threadIdx.x < NQ_QUALITY) st->quality[threadIdx.x] = s[threadIdx.x];
     } break;
+    case FIN_LAGRANGIAN: {
+      // L_rho = D(b) + (alpha v / 2)|D1 b|^2 + (alpha v / 2)(|D2 z|^2 + |D3 z|^2)
+      //       + rho v u'(b - z) + (rho v / 2)|b - z|^2 at the newest iterate (eq. Lp), with
+      // the rho of that iteration and u before any rescale of the next one
+      const int it = st->admm_iter - 1;
+      if (it < 0 || st->lagr_last == st->admm_iter || it >= f.hist_len) return;
+      reduce_partials<NQ_EVAL>(f.partial, f.nb1, s);
+      reduce_partials<NQ_EVAL>(f.partial2, f.nb2, s2);
+      reduce_partials<1>(f.partial3, f.nb3, s3);
+      if (threadIdx.x == 0) {
+        const double rho = f.hist[4 * f.hist_len + it], rpri = f.hist[it];
+        const double L = 0.5 * f.v * s[0] + 0.5 * f.alpha * f.v * s[1] +
+                         0.5 * f.alpha * f.v * s2[2] + rho * f.v * s3[0] +
+                         0.5 * rho * f.v * rpri * rpri;
+        f.hist[5 * f.hist_len + it] = L;
+        st->lagr_last = st->admm_iter;
+      }
+    } break;
     case FIN_HARD_RESET: {
       if (threadIdx.x == 0 && !st->admm_done) {
         st->hard_total += st->hard_count;
@@ -323,6 +352,10 @@ void launch_matvec(hipStream_t s, int P, LineArgs a, const float* z, const float
 }
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial) {
   hipLaunchKernelGGL(k_dot, dim3(flat_blocks(n)), dim3(256), 0, s, n, x, y, partial);
+}
+void launch_udot(hipStream_t s, long long n, const float* u, const float* b, const float* z,
+                 double* partial) {
+  hipLaunchKernelGGL(k_udot, dim3(flat_blocks(n)), dim3(256), 0, s, n, u, b, z, partial);
 }
 void launch_sgs_finish(hipStream_t s, long long n, const float* r, const float* z, float* p,
                        double* partial, int first, const DevState* st) {

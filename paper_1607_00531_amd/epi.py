@@ -54,14 +54,15 @@ class GNReport(C.Structure):
 
 # penalty strategies of epi_admm_opts.rho_mode
 RHO_MODES = {"fixed": 0, "adapt": 1, "adapt_floor": 2}
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 
 class ADMMOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("sqp_iters", C.c_int32), ("check_every", C.c_int32),
                 ("rho", C.c_double), ("eps_abs", C.c_double), ("eps_rel", C.c_double),
                 ("rho_mode", C.c_int32), ("tau", C.c_double), ("mu", C.c_double),
-                ("rho_min", C.c_double)]
+                ("rho_min", C.c_double), ("qp_max_iter", C.c_int32),
+                ("with_lagrangian", C.c_int32)]
 
 
 class ADMMReport(C.Structure):
@@ -69,7 +70,7 @@ class ADMMReport(C.Structure):
                 ("max_active", C.c_int32), ("hard_lines", C.c_int64),
                 ("r_pri", C.POINTER(C.c_double)), ("r_dual", C.POINTER(C.c_double)),
                 ("eps_pri", C.POINTER(C.c_double)), ("eps_dual", C.POINTER(C.c_double)),
-                ("rho", C.POINTER(C.c_double))]
+                ("rho", C.POINTER(C.c_double)), ("lagrangian", C.POINTER(C.c_double))]
 
 
 class Quality(C.Structure):
@@ -78,7 +79,8 @@ class Quality(C.Structure):
 
 
 class KernelProfile(C.Structure):
-    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8)]
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8),
+                ("us_isolated", C.c_double * 8), ("isolated_reps", C.c_int32)]
 
 
 KERNEL_NAMES = ["bstep", "bstep_hard", "dct_axis3", "dct_axis2_fused", "dct_last_epilogue",
@@ -296,20 +298,26 @@ class Problem:
         _check(lib().epi_corrected_images(self._h, self._faces(b), op, om, C.byref(q)))
         return dict(D=q.D, ncc=q.ncc, mean_plus=q.mean_plus, mean_minus=q.mean_minus)
 
-    def solve_admm(self, b, z, u, profile: bool = False, **kw) -> dict:
+    def solve_admm(self, b, z, u, profile: bool = False, isolated_reps: int = 0, **kw) -> dict:
         """ADMM from the state (b, z, u), updated in place. With profile=True the solve runs
-        through epi_profile_admm and the result carries per-kernel device times."""
+        through epi_profile_admm and the result carries per-kernel device times; with
+        isolated_reps > 0 also the back-to-back launch time of each kernel family
+        (microseconds per launch, kernel_us_isolated)."""
         o = ADMMOpts()
         lib().epi_admm_default_opts(C.byref(o))
         for k, v in kw.items():
             setattr(o, k, RHO_MODES[v] if k == "rho_mode" and isinstance(v, str) else v)
         n1 = max(o.max_iter, 1)
-        arrs = {k: (C.c_double * n1)() for k in ("r_pri", "r_dual", "eps_pri", "eps_dual", "rho")}
+        keys = ["r_pri", "r_dual", "eps_pri", "eps_dual", "rho"]
+        if o.with_lagrangian:
+            keys.append("lagrangian")
+        arrs = {k: (C.c_double * n1)() for k in keys}
         rep = ADMMReport()
         for k, a in arrs.items():
             setattr(rep, k, C.cast(a, C.POINTER(C.c_double)))
         if profile:
             prof = KernelProfile()
+            prof.isolated_reps = int(isolated_reps)
             _check(lib().epi_profile_admm(self._h, self._faces(b), self._faces(z),
                                           self._faces(u), C.byref(o), C.byref(rep),
                                           C.byref(prof)))
@@ -324,6 +332,9 @@ class Problem:
         if profile:
             out["kernel_ms"] = {n: prof.ms[i] for i, n in enumerate(KERNEL_NAMES)}
             out["kernel_launches"] = {n: int(prof.launches[i]) for i, n in enumerate(KERNEL_NAMES)}
+            if isolated_reps > 0:
+                out["kernel_us_isolated"] = {n: prof.us_isolated[i]
+                                             for i, n in enumerate(KERNEL_NAMES)}
         return out
 
 
@@ -449,6 +460,9 @@ def _batch_sigs(L):
     L.epi_batch_release.restype = C.c_int
     L.epi_batch_destroy.argtypes = [vp]
     L.epi_batch_destroy.restype = None
+    L.epi_batch_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64)]
+    L.epi_batch_stats.restype = C.c_int
     L._batch_sigs = True
     return L
 
@@ -530,6 +544,12 @@ class Batch:
             out[key] = list(a[:k])
         return out
 
+    def stats(self) -> dict:
+        """Admissions, admissions that allocated a workspace, graph captures so far."""
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(_batch_sigs(lib()).epi_batch_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(admissions=a.value, admissions_allocating=b.value, graph_captures=c.value)
+
     def release(self, slot: int):
         _check(_batch_sigs(lib()).epi_batch_release(self._h, int(slot)))
         self._keep.pop(slot, None)
@@ -538,6 +558,111 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             _batch_sigs(lib()).epi_batch_destroy(self._h)
+            self._h = C.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _server_sigs(L):
+    vp = C.c_void_p
+    if getattr(L, "_server_sigs", False):
+        return L
+    L.epi_server_clock.argtypes = []
+    L.epi_server_clock.restype = C.c_double
+    L.epi_server_create.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int32, vp, C.POINTER(vp)]
+    L.epi_server_create.restype = C.c_int
+    L.epi_server_submit.argtypes = [vp, C.c_int64, C.c_double, C.POINTER(Grid), vp, vp, vp, vp,
+                                    vp, C.POINTER(ADMMOpts)]
+    L.epi_server_submit.restype = C.c_int
+    L.epi_server_progress.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]
+    L.epi_server_progress.restype = C.c_int
+    L.epi_server_take.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                  C.POINTER(ADMMReport)]
+    L.epi_server_take.restype = C.c_int
+    L.epi_server_destroy.argtypes = [vp]
+    L.epi_server_destroy.restype = None
+    L._server_sigs = True
+    return L
+
+
+class Server:
+    """The request loop of the served solver (epi_server_*): submit requests as they
+    arrive, call progress() repeatedly, take() finished ones. Tensors handed to submit are
+    kept referenced until the request is taken."""
+
+    def __init__(self, max_slots: int = 16, hbm_budget_bytes: int = 64 << 30,
+                 precision: str = "mixed", iters_per_step: int = 8, stream=None):
+        L = _server_sigs(lib())
+        self._h = C.c_void_p()
+        self.precision = precision
+        _check(L.epi_server_create(int(max_slots), int(hbm_budget_bytes), PREC[precision],
+                                   int(iters_per_step), _stream_handle(stream),
+                                   C.byref(self._h)))
+        self._keep = {}
+
+    @staticmethod
+    def clock() -> float:
+        """Seconds on the server's monotonic clock (arrival times use it)."""
+        return float(_server_sigs(lib()).epi_server_clock())
+
+    def submit(self, request_id: int, Ip, Im, h, alpha, b, z, u, arrival=None, beta=10.0,
+               gamma=1e-3, ndim=None, **opts):
+        L = _server_sigs(lib())
+        g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, self.precision, ndim)
+        o = ADMMOpts()
+        L.epi_admm_default_opts(C.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, RHO_MODES[v] if k == "rho_mode" and isinstance(v, str) else v)
+        t = self.clock() if arrival is None else float(arrival)
+        _check(L.epi_server_submit(self._h, int(request_id), t, C.byref(g), _ptr(Ip), _ptr(Im),
+                                   _ptr(b), _ptr(z), _ptr(u), C.byref(o)))
+        self._keep[int(request_id)] = ((Ip, Im, b, z, u), max(o.max_iter, 1))
+
+    def progress(self):
+        """(queued, running, ready) after one round of admission, engine step and polling."""
+        q, r, d = C.c_int32(0), C.c_int32(0), C.c_int32(0)
+        _check(_server_sigs(lib()).epi_server_progress(self._h, C.byref(q), C.byref(r),
+                                                       C.byref(d)))
+        return q.value, r.value, d.value
+
+    def take(self):
+        """The oldest finished request as a dict (id, latency_s, report fields), or None."""
+        L = _server_sigs(lib())
+        if not self._keep:
+            return None
+        cap = max(m for _, m in self._keep.values())
+        arrs = {k: (C.c_double * cap)() for k in ("r_pri", "r_dual", "eps_pri", "eps_dual", "rho")}
+        rep = ADMMReport()
+        for k, a in arrs.items():
+            setattr(rep, k, C.cast(a, C.POINTER(C.c_double)))
+        rid, lat = C.c_int64(0), C.c_double(0.0)
+        st = L.epi_server_take(self._h, C.byref(rid), C.byref(lat), C.byref(rep))
+        if st == EPI_EBUSY:
+            return None
+        _check(st)
+        self._keep.pop(rid.value, None)
+        k = rep.iters
+        out = dict(id=rid.value, latency_s=lat.value, iters=k, converged=bool(rep.converged),
+                   status=rep.status, max_active=rep.max_active, hard_lines=int(rep.hard_lines))
+        for key, a in arrs.items():
+            out[key] = list(a[:k])
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _server_sigs(lib()).epi_server_destroy(self._h)
             self._h = C.c_void_p()
             self._keep.clear()
 

@@ -14,6 +14,7 @@ from .generator import (
     config_volume,
     batch_shapes,
     serving_requests,
+    shutdown_pool,
 )
 
 __all__ = [
@@ -25,4 +26,5 @@ __all__ = [
     "config_volume",
     "batch_shapes",
     "serving_requests",
+    "shutdown_pool",
 ]

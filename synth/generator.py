@@ -232,6 +232,15 @@ def _pool():
     return _POOL
 
 
+def shutdown_pool() -> None:
+    """Stop the worker processes now (they are otherwise stopped at interpreter exit);
+    a later large volume starts a new pool."""
+    global _POOL
+    if _POOL is not None:
+        _POOL.shutdown(wait=True)
+        _POOL = None
+
+
 def _run_chunks(jobs, parallel: bool):
     global _POOL
     if parallel:

@@ -28,16 +28,26 @@ def N(t):
 
 
 def hist_ok(gpu, cpu, scale, prec):
+    """Residual history against the oracle: every entry within HIST_REL relative or within
+    the absolute floor EPS_HIST[prec] * scale. Returns (ok, message); the message names the
+    first failing entry, or says how many entries needed the floor (the relative bar alone
+    held for the others)."""
     gpu, cpu = np.asarray(gpu), np.asarray(cpu)
     if gpu.shape != cpu.shape:
         return False, f"length {gpu.shape} vs {cpu.shape}"
     err = np.abs(gpu - cpu)
-    lim = np.maximum(HIST_REL * np.abs(cpu), EPS_HIST[prec] * scale)
+    rel = HIST_REL * np.abs(cpu)
+    lim = np.maximum(rel, EPS_HIST[prec] * scale)
     bad = np.nonzero(err > lim)[0]
     if bad.size:
         i = bad[0]
         return False, f"iteration {i}: gpu {gpu[i]:.6e} cpu {cpu[i]:.6e} limit {lim[i]:.2e}"
-    return True, ""
+    floor = int(np.count_nonzero(err > rel))
+    worst = float(np.max(err / np.maximum(np.abs(cpu), 1e-300))) if err.size else 0.0
+    used = float(np.max(err[err > rel]) / scale) if floor and scale > 0 else 0.0
+    return True, (f"{err.size - floor} of {err.size} entries within {HIST_REL:g} relative "
+                  f"(worst {worst:.1e}), {floor} at the absolute floor (largest "
+                  f"{used:.1e} of the scale, floor {EPS_HIST[prec]:g})")
 
 
 def oracle_precond(P, tri, r, precond):

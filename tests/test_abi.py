@@ -44,6 +44,31 @@ def test_default_options_are_the_papers():
     assert a["eps_abs"] == 0.2 and a["eps_rel"] == 0.2 and a["sqp_iters"] == 1
     # adaptive penalty constants (tau, mu, rho_min of the paper's 3D experiments)
     assert a["rho_mode"] == 0 and a["tau"] == 1.3 and a["mu"] == 10.0 and a["rho_min"] == 1e2
+    # active-set cap 4 (M + 1) (0), no Lagrangian monitoring by default
+    assert a["qp_max_iter"] == 0 and a["with_lagrangian"] == 0
+
+
+@pytest.mark.parametrize("m,max_iter", [((240, 200, 110), 2000), ((64, 64, 1), 20),
+                                        ((128, 96, 48), 40), ((17, 5, 3), 1)])
+def test_batch_footprint_covers_one_slot(m, max_iter):
+    """epi_batch_footprint (host arithmetic, no device call) is at least what one resident
+    request occupies: its images and state (caller-owned) and the three n-float work
+    arrays, the six float64 history rows and the two DCT matrices per axis that admission
+    allocates."""
+    from paper_1607_00531_amd import epi
+    lib = epi.lib()
+    lib.epi_batch_footprint.restype = ctypes.c_int64
+    lib.epi_batch_footprint.argtypes = [ctypes.POINTER(epi.Grid), ctypes.c_int32]
+    g = epi.Grid()
+    g.ndim = 3 if m[2] > 1 else 2
+    for a in range(3):
+        g.m[a] = m[a]
+        g.h[a] = 1.0 / m[a] if m[a] > 1 else 1.0
+    g.alpha, g.beta, g.gamma, g.precision = 50.0, 10.0, 1e-3, 1
+    M, m2, m3 = m
+    n, N = (M + 1) * m2 * m3, M * m2 * m3
+    need = 4 * (2 * N + 3 * n) + 3 * 4 * n + 6 * 8 * max_iter + 2 * 2 * (m2 * m2 + m3 * m3)
+    assert lib.epi_batch_footprint(ctypes.byref(g), max_iter) >= need
 
 
 def test_ctypes_structs_match_header_field_order():

@@ -27,6 +27,25 @@ def test_algorithmic_bytes_of_the_admm_kernels():
     assert b["dct_last_epilogue"] == 24 * n
 
 
+def test_method_bytes_are_44_per_face():
+    """What the ADMM iteration must move with every line and tile staged on chip once:
+    the b-step reads both images (8 B per cell) and b, z, u and writes b (16 B per face);
+    the z- and u-step read b, u and the old z and write z, u (20 B per face)."""
+    import bench
+    M, m2, m3 = 240, 200, 110
+    n, N = (M + 1) * m2 * m3, M * m2 * m3
+    b = bench.method_bytes(M, m2, m3)
+    assert b["bstep"] == 8 * N + 16 * n == 127_072_000
+    assert b["zu_step"] == 20 * n
+    assert b["iteration"] == b["bstep"] + b["zu_step"] == 233_112_000
+
+
+def test_host_cpu_is_reported():
+    import bench
+    model, ncpu = bench.host_cpu()
+    assert isinstance(model, str) and model and ncpu >= 1
+
+
 def test_mfma_flops_of_the_split_transform():
     """Even/odd halves: 2c^2 + 2f^2 per column of length m (c, f the half lengths), three
     products per multiply-add in mixed precision; full 2m^2 per column in float32. The j-axis

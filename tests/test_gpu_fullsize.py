@@ -2,22 +2,32 @@
 configuration the benchmark times (graph-captured iterations, check_every = 32):
 
 * 240 x 200 x 110 cells, PE along the first axis (5,302,000 faces, 241 faces per line):
-  objective and gradient at the true field and at zero; ADMM steps in both precisions.
-* 128 x 128 x 64 cells, PE along the second axis (1,056,768 faces): two GN-PCG steps with
-  the block-Jacobi preconditioner, ADMM steps, and every preconditioner applied once
-  (symmetric Gauss-Seidel: 191 dependent levels per sweep).
+  objective and gradient at the true field and at zero; the configuration's 30 ADMM
+  iterations from zero in the benchmark's precision with, at every iteration, one GPU
+  step from the oracle's state; single steps in float32; and the solve the benchmark
+  times (from zero to the relative residual 1e-3, eq. admmStop with eps_abs = 0,
+  eps_rel = 1e-3) in both precisions against the stored oracle solve of
+  tests/oracle_samples/.
+* 128 x 128 x 64 cells, PE along the second axis (1,056,768 faces): 30 GN-PCG iterations
+  (block-Jacobi) against the stored oracle run; 30 ADMM iterations with a single step from
+  the oracle's state at each, in both precisions; every preconditioner applied once
+  (symmetric Gauss-Seidel: 191 dependent levels per sweep). At this size ADMM with
+  rho = 1e3 does not reach 1e-3 within 2000 iterations (the oracle's primal residual
+  stalls near 5 times its tolerance), so the converged comparison also runs on two 3D
+  volumes that do converge: 64 x 64 x 64 (PE axis 3) and 120 x 100 x 56 (PE axis 1).
 
-ADMM is compared step by step: from each of the oracle's first iterates (b^k, z^k, u^k) the
-GPU takes one iteration and must land on the oracle's (b^k+1, z^k+1, u^k+1) within the field
-tolerance, with that iteration's residuals within the history tolerance. Whole trajectories
-are not compared at these sizes: with rho v ~ 2e-4 against a data term linearised at b^k,
-the b-step map amplifies differences in the early iterations (one-step differences of
-~1e-4 voxel grow to ~3e-3 voxel after four iterations, identically in float32 and in
-mixed precision), so a trajectory comparison would measure the map's sensitivity to
-float32 rounding rather than the correctness of a step. The smaller trajectory tests of
-test_gpu_parity.py compare whole trajectories.
-
-The oracle runs once per module (several seconds of NumPy at these sizes)."""
+Bars: single steps 1e-3 voxel on every face; objective 1e-5 relative; residual histories
+1e-4 relative or the float32 floor of gpu_common.hist_ok (the message says how many
+entries needed the floor); fields of whole trajectories and of converged solutions 1e-3
+voxel on every face in float32, and for z in both precisions. The b-step is discontinuous
+in the state wherever a displacement crosses a knot of the linear image model
+(test_oracle_float32_sensitivity.py shows it with the oracle alone). The split-bfloat16
+z-step (the arithmetic the mixed-precision solver is specified with) leaves the state
+~1e-5 voxel from the oracle's per iteration, so such crossings happen at other iterations
+than in the oracle, and b and u then differ locally by up to a few 1e-3 voxel until the
+transient dies out; they are held to the oracle's own max|b - z| at that iterate, the
+pointwise size of the primal residual (see _assert_fields). Every test prints its
+measured errors and the share of faces beyond 1e-3 voxel."""
 import numpy as np
 import pytest
 
@@ -29,12 +39,16 @@ pytestmark = pytest.mark.gpu
 
 V240 = "3d_240x200x110"
 V128 = "3d_128x128x64"
-ADMM_ITERS = 4
+ADMM_STEPS = 4          # single steps from the oracle's first iterates
+TRAJ = 30               # iterations of the configurations' side-by-side runs
+TOL = 1e-3              # relative residual of the converged comparison
+MAX_ITER = 2000
 
 
-def _problem(v, alpha, prec):
+def _problem(v, name, prec):
     from paper_1607_00531_amd import Problem
-    return Problem(T(v.Ip), T(v.Im), v.h, alpha, beta=CONFIGS[V240]["beta"], precision=prec)
+    c = CONFIGS[name]
+    return Problem(T(v.Ip), T(v.Im), v.h, c["alpha"], beta=c["beta"], precision=prec)
 
 
 def _oracle_steps(P, rho, iters):
@@ -52,21 +66,32 @@ def _oracle_steps(P, rho, iters):
     return states, res
 
 
+def _vox(P, gpu, cpu):
+    return float(np.abs(N(gpu).reshape(P.L, -1) - cpu.reshape(P.L, -1)).max() / P.hp)
+
+
 @pytest.fixture(scope="module")
 def c3():
     v = config_volume(V240, 0)
-    alpha, rho = CONFIGS[V240]["alpha"], CONFIGS[V240]["rho"]
-    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
-    return v, P, _oracle_steps(P, rho, ADMM_ITERS)
+    c = CONFIGS[V240]
+    P = O.make_problem(v.Ip, v.Im, v.h, c["alpha"])
+    steps = _oracle_steps(P, c["rho"], ADMM_STEPS)
+    return v, P, steps
 
 
 @pytest.fixture(scope="module")
 def c2():
     v = config_volume(V128, 0)
-    alpha, rho = CONFIGS[V128]["alpha"], CONFIGS[V128]["rho"]
-    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
-    gn = O.solve_gnpcg(P, max_iter=2, use_stopping=False)
-    return v, P, gn, _oracle_steps(P, rho, ADMM_ITERS)
+    P = O.make_problem(v.Ip, v.Im, v.h, CONFIGS[V128]["alpha"])
+    return v, P, None
+
+
+def _stored(name):
+    """An oracle reference written by a script of tests/oracle_samples/ (only the oracle
+    and the generator run there; the FP64 solve takes minutes at these sizes)."""
+    import os
+    return np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_samples",
+                                name))
 
 
 def test_c3_shape_is_the_benchmark_workload(c3):
@@ -76,8 +101,7 @@ def test_c3_shape_is_the_benchmark_workload(c3):
 
 def test_c3_objective_and_gradient(c3):
     v, P, _ = c3
-    alpha = CONFIGS[V240]["alpha"]
-    with _problem(v, alpha, "mixed") as pr:
+    with _problem(v, V240, "mixed") as pr:
         for bb in (v.b_true.reshape(P.L, -1), np.zeros((P.L, P.M + 1))):
             g = T(np.zeros(pr.shape_faces))
             t = pr.objective(T(bb.reshape(pr.shape_faces)), True, grad=g)
@@ -89,29 +113,8 @@ def test_c3_objective_and_gradient(c3):
             assert err <= 2e-4 * np.abs(go).max(), err / np.abs(go).max()
 
 
-EPS32 = 2.0 ** -24
-
-
-def _kappa_bound(P, b, z, u, rho):
-    """Upper bound on the condition number of the b-step line systems at this state:
-    G = H_D + alpha v D1'D1 + rho v I with H_D and D1'D1 positive semidefinite, so
-    lambda_min >= rho v, and lambda_max is at most the largest Gershgorin row sum."""
-    import oracle.epi_oracle as OE
-    Gd, Go, _, _ = OE._qp_data(P, b, z, u, rho)
-    row = Gd.copy()
-    row[:, :-1] += np.abs(Go)
-    row[:, 1:] += np.abs(Go)
-    return float(row.max()) / (rho * P.v)
-
-
 def _check_admm_steps(pr, P, ref, prec):
-    """One GPU iteration from each oracle iterate. Histories: relative 1e-4, or the
-    float32 bound of the b-step. A float32 solve of a system with condition kappa
-    (assembled in float32, as the method prescribes) is accurate to c eps kappa |x| with x
-    the step b^k+1 - b^k (c = 4 here); the z-step is a contraction, so r_dual = rho v
-    |z^k+1 - z^k| moves by at most rho v c eps kappa |x| and r_pri = |b - z| by twice
-    c eps kappa |x|. At 240 x 200 x 110, rho v ~ 1.9e-4 against alpha v / h_p^2 ~ 0.55 gives
-    kappa ~ 1.2e4."""
+    """One GPU iteration from each oracle iterate lands on the oracle's next iterate."""
     states, res = ref
     sh = pr.shape_faces
     for k in range(len(res)):
@@ -119,54 +122,228 @@ def _check_admm_steps(pr, P, ref, prec):
         rep = pr.solve_admm(b, z, u, rho=1e3, max_iter=1, eps_abs=0.0, eps_rel=0.0,
                             check_every=32)
         assert rep["iters"] == 1
-        errs = {name: np.abs(N(gpu).reshape(P.L, -1) - cpu).max() / P.hp
-                for name, gpu, cpu in zip("bzu", (b, z, u), states[k + 1])}
+        errs = {name: _vox(P, gpu, cpu) for name, gpu, cpu in zip("bzu", (b, z, u), states[k + 1])}
         assert max(errs.values()) <= FIELD_VOX, (k, errs)
         bo, zo = states[k + 1][0], states[k + 1][1]
         scale = max(np.linalg.norm(bo), np.linalg.norm(zo))
-        step = np.linalg.norm(bo - states[k][0])
-        solve = 4 * EPS32 * _kappa_bound(P, *states[k], 1e3) * step
         rp, rd, _, _ = res[k]
-        for key, r, s, bound in (("r_pri", rp, scale, 2 * solve),
-                                 ("r_dual", rd, scale * 1e3 * P.v, 1e3 * P.v * solve)):
+        for key, r, s in (("r_pri", rp, scale), ("r_dual", rd, scale * 1e3 * P.v)):
             ok, msg = hist_ok(rep[key], [r], s, prec)
-            assert ok or abs(rep[key][0] - r) <= bound, (k, key, msg, bound)
+            assert ok, (k, key, msg)
 
 
-@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+def _steps_and_trajectory(pr, P, prec, iters, rho=1e3):
+    """The configurations' side-by-side run of `iters` ADMM iterations from zero, with the
+    oracle advanced alongside. At every iteration the GPU also takes one step from the
+    oracle's current state, which must land on the oracle's next state within the field bar
+    (single steps, the per-step criterion); the GPU's own trajectory is advanced one
+    iteration at a time (the same kernels as one solve: results do not depend on the
+    polling interval). Returns the trajectory's field errors, its share of faces beyond
+    the bar, and the histories' messages."""
+    sh = pr.shape_faces
+    b, z, u = (T(np.zeros(sh)) for _ in range(3))
+    bo = np.zeros((P.L, P.M + 1))
+    zo, uo = bo.copy(), bo.copy()
+    hist = {"r_pri": [], "r_dual": []}
+    gpu_hist = {"r_pri": [], "r_dual": []}
+    worst_step = 0.0
+    for k in range(iters):
+        bs, zs, us = (T(x.reshape(sh)) for x in (bo, zo, uo))
+        rs = pr.solve_admm(bs, zs, us, rho=rho, max_iter=1, eps_abs=0.0, eps_rel=0.0,
+                           check_every=1)
+        rt = pr.solve_admm(b, z, u, rho=rho, max_iter=1, eps_abs=0.0, eps_rel=0.0,
+                           check_every=1)
+        bn, _, _ = O.bstep(P, bo, zo, uo, rho)
+        zn = O.zstep(P, bn + uo, rho)
+        un = uo + bn - zn
+        rp, rd, _, _ = O.admm_residuals(P, bn, zn, zo, un, rho, 0.0, 0.0)
+        bo, zo, uo = bn, zn, un
+        hist["r_pri"].append(rp)
+        hist["r_dual"].append(rd)
+        for key in hist:
+            gpu_hist[key].append(rt[key][0])
+        errs = {name: _vox(P, gpu, cpu) for name, gpu, cpu in zip("bzu", (bs, zs, us), (bo, zo, uo))}
+        worst_step = max(worst_step, max(errs.values()))
+        assert max(errs.values()) <= FIELD_VOX, ("single step", k, errs)
+        scale = max(np.linalg.norm(bo), np.linalg.norm(zo))
+        for key, r, sc in (("r_pri", rp, scale), ("r_dual", rd, scale * rho * P.v)):
+            ok, msg = hist_ok(rs[key], [r], sc, prec)
+            assert ok, ("single step", k, key, msg)
+    errs, frac = {}, {}
+    for name, gpu, cpu in zip("bzu", (b, z, u), (bo, zo, uo)):
+        e = np.abs(N(gpu).reshape(P.L, -1) - cpu) / P.hp
+        errs[name] = float(e.max())
+        frac[name] = float(np.count_nonzero(e > FIELD_VOX)) / e.size
+    scale = max(np.linalg.norm(bo), np.linalg.norm(zo))
+    msgs = {}
+    for key, sc in (("r_pri", scale), ("r_dual", scale * rho * P.v)):
+        ok, msgs[key] = hist_ok(gpu_hist[key], hist[key], sc, prec)
+        assert ok, ("trajectory", key, msgs[key])
+    bz = float(np.abs(bo - zo).max() / P.hp)
+    print(f"{prec}: worst single step {worst_step:.2e} voxel; trajectory fields {errs}, "
+          f"faces beyond {FIELD_VOX:g} voxel {frac}, oracle max|b - z| {bz:.2e} voxel, {msgs}")
+    return errs, frac, (b, z, u), bo, bz
+
+
+def _assert_fields(errs, prec, bz):
+    """Fields of a whole trajectory or of a stopping iterate. z, the smooth consensus field,
+    is within the field bar on every face in both precisions, and so are b and u in float32.
+    With the split-bfloat16 z-step the state differs from the oracle's by ~1e-5 voxel per
+    iteration, enough for knot crossings of the b-step to happen at other iterations than in
+    the oracle (see the module docstring): b and u are then held, on every face, to the
+    oracle's own max|b - z| at that iterate (bz, voxels), the pointwise size of the primal
+    residual, which bounds how far b lies from the consensus it is converging to."""
+    assert errs["z"] <= FIELD_VOX, errs
+    lim = FIELD_VOX if prec == "fp32" else max(FIELD_VOX, bz)
+    for k in "bu":
+        assert errs[k] <= lim, (k, errs, lim)
+
+
+@pytest.mark.parametrize("prec", ["fp32"])
 def test_c3_admm_steps(c3, prec):
-    v, P, ref = c3
-    with _problem(v, CONFIGS[V240]["alpha"], prec) as pr:
-        _check_admm_steps(pr, P, ref, prec)
+    v, P, steps = c3
+    with _problem(v, V240, prec) as pr:
+        _check_admm_steps(pr, P, steps, prec)
 
 
-def test_c2_gnpcg_steps(c2):
-    v, P, (bo, ro), _ = c2
-    with _problem(v, CONFIGS[V128]["alpha"], "mixed") as pr:
+def test_c3_admm_steps_and_trajectory(c3):
+    """The configuration's side-by-side run at 240 x 200 x 110 in the benchmark's
+    precision: 30 iterations from zero, with a single step from the oracle's state at each
+    iteration."""
+    v, P, _ = c3
+    with _problem(v, V240, "mixed") as pr:
+        errs, frac, (b, _, _), bo, bz = _steps_and_trajectory(pr, P, "mixed", TRAJ)
+        _assert_fields(errs, "mixed", bz)
+        J = pr.objective(b, False)["J"]
+    Jo = O.objective(P, bo, False)["J"]
+    assert abs(J - Jo) <= J_REL * abs(Jo), (J, Jo)
+
+
+def test_c2_gnpcg_trajectory(c2):
+    """30 GN-PCG iterations (block-Jacobi, eta = 0.1, at most 30 PCG iterations) from zero
+    against the stored oracle run (tests/oracle_samples/make_gnpcg_trajectory.py): every J
+    value at 1e-5 relative, the PCG iteration counts exactly, the field at 16384 fixed
+    faces within 1e-3 voxel and its norm at 1e-5 relative."""
+    v, P, _ = c2
+    ref = _stored("gnpcg_128x128x64_seed0.npz")
+    sums = np.array([float(np.sum(v.Ip)), float(np.sum(v.Im))])
+    np.testing.assert_allclose(sums, ref["image_sums"], rtol=1e-12)   # same generator
+    with _problem(v, V128, "mixed") as pr:
         b = T(np.zeros(pr.shape_faces))
-        rep = pr.solve_gnpcg(b, max_iter=2, use_stopping=0)
-        assert rep["iters"] == ro.iters == 2
-        np.testing.assert_allclose(rep["J"], ro.J, rtol=0, atol=J_REL * ro.J[0])
-        assert rep["pcg_iters"] == ro.pcg_iters
-        assert np.abs(N(b) - bo.reshape(N(b).shape)).max() / P.hp <= FIELD_VOX
+        rep = pr.solve_gnpcg(b, max_iter=TRAJ, use_stopping=0)
+    assert rep["iters"] == int(ref["iters"]) == TRAJ
+    Jg, Jo = np.asarray(rep["J"]), ref["J"]
+    rel = np.abs(Jg - Jo) / np.abs(Jo)
+    print(f"J relative error max {rel.max():.2e}; PCG {rep['pcg_iters']}")
+    assert rel.max() <= J_REL, (int(rel.argmax()), rel.max())
+    assert rep["pcg_iters"] == [int(x) for x in ref["pcg_iters"]]
+    bg = N(b).reshape(-1)
+    err = np.abs(bg[ref["idx"]] - ref["b"]).max() / P.hp
+    assert err <= FIELD_VOX, err
+    nb = float(np.linalg.norm(bg))
+    assert abs(nb - float(ref["b_norm"])) <= J_REL * float(ref["b_norm"]), (nb, float(ref["b_norm"]))
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp32"])
-def test_c2_admm_steps(c2, prec):
-    v, P, _, ref = c2
-    with _problem(v, CONFIGS[V128]["alpha"], prec) as pr:
-        _check_admm_steps(pr, P, ref, prec)
+def test_c2_admm_steps_and_trajectory(c2, prec):
+    """The configuration's side-by-side run at 128 x 128 x 64: 30 ADMM iterations from zero
+    with a single step from the oracle's state at each iteration."""
+    v, P, _ = c2
+    with _problem(v, V128, prec) as pr:
+        errs, frac, _, _, bz = _steps_and_trajectory(pr, P, prec, TRAJ)
+    _assert_fields(errs, prec, bz)
+
+
+CONVERGED = {"64x64x64": ((64, 64, 64), 2, 0), "120x100x56": ((120, 100, 56), 0, 3)}
+
+
+@pytest.fixture(scope="module")
+def converged_refs():
+    """Oracle solves from zero to the relative residual 1e-3 (172 and 117 iterations)."""
+    from synth import generate
+    out = {}
+    for name, (m, pe, seed) in CONVERGED.items():
+        v = generate(seed, m, pe)
+        P = O.make_problem(v.Ip, v.Im, v.h, 50.0)
+        out[name] = (v, P, O.solve_admm(P, rho=1e3, max_iter=MAX_ITER, eps_abs=0.0,
+                                        eps_rel=TOL))
+    return out
+
+
+def _check_converged(pr, P, prec, iters_ref, fields_ref, hist_ref, bz_ref, idx=None):
+    """GPU solve from zero to the relative residual 1e-3 against the oracle's: both
+    converge and the iteration counts agree within 2; the residual histories over the
+    common iterations are at their bars; the fields (at idx, or everywhere) as in
+    _assert_fields, with bz_ref the oracle's max|b - z| at its stopping iterate."""
+    sh = pr.shape_faces
+    b, z, u = (T(np.zeros(sh)) for _ in range(3))
+    rep = pr.solve_admm(b, z, u, rho=1e3, max_iter=MAX_ITER, eps_abs=0.0, eps_rel=TOL,
+                        check_every=32)
+    errs, frac = {}, {}
+    for name, gpu, cpu in zip("bzu", (b, z, u), fields_ref):
+        g = N(gpu).reshape(-1)
+        g = g if idx is None else g[idx]
+        e = np.abs(g - cpu.reshape(-1)) / P.hp
+        errs[name] = float(e.max())
+        frac[name] = float(np.count_nonzero(e > FIELD_VOX)) / e.size
+    n = min(rep["iters"], len(hist_ref[0]))
+    scale = max(np.linalg.norm(N(b)), np.linalg.norm(N(z)))
+    msgs = {}
+    for key, ref, s in (("r_pri", hist_ref[0], scale), ("r_dual", hist_ref[1], scale * 1e3 * P.v)):
+        ok, msgs[key] = hist_ok(rep[key][:n], ref[:n], s, prec)
+        assert ok, (key, msgs[key])
+    print(f"{prec}: {rep['iters']} iterations (oracle {iters_ref}), fields {errs}, faces "
+          f"beyond {FIELD_VOX:g} voxel {frac}, oracle max|b - z| {bz_ref:.2e} voxel, {msgs}")
+    assert rep["converged"]
+    assert abs(rep["iters"] - iters_ref) <= 2, (rep["iters"], iters_ref)
+    _assert_fields(errs, prec, bz_ref)
+    return b
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+@pytest.mark.parametrize("name", list(CONVERGED))
+def test_admm_converged_3d(converged_refs, name, prec):
+    """The metric's solve (from zero to the relative residual 1e-3) on two 3D volumes
+    that converge within the cap, against the oracle's own converged solve."""
+    v, P, (bo, zo, uo, ro) = converged_refs[name]
+    assert ro.converged
+    bz = float(np.abs(bo - zo).max() / P.hp)
+    from paper_1607_00531_amd import Problem
+    with Problem(T(v.Ip), T(v.Im), v.h, 50.0, precision=prec) as pr:
+        _check_converged(pr, P, prec, ro.iters, (bo, zo, uo), (ro.r_pri, ro.r_dual), bz)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp32"])
+def test_c3_admm_converged_against_stored_oracle(prec):
+    """The benchmark's solve at 240 x 200 x 110 (seed 3) against the oracle's converged
+    solve stored by tests/oracle_samples/make_admm_converged.py: iteration count within 2,
+    b, z, u at 16384 fixed faces within 1e-3 voxel, the histories, the norm of b and
+    the objective at b."""
+    ref = _stored("admm_240x200x110_seed3.npz")
+    v = config_volume(V240, 3)
+    sums = np.array([float(np.sum(v.Ip)), float(np.sum(v.Im))])
+    np.testing.assert_allclose(sums, ref["image_sums"], rtol=1e-12)   # same generator
+    P = O.make_problem(v.Ip, v.Im, v.h, 50.0)
+    assert int(ref["converged"]) == 1
+    with _problem(v, V240, prec) as pr:
+        b = _check_converged(pr, P, prec, int(ref["iters"]), (ref["b"], ref["z"], ref["u"]),
+                             (ref["r_pri"], ref["r_dual"]), float(ref["bz_max_vox"]),
+                             idx=ref["idx"])
+        J = pr.objective(b, False)["J"]
+    assert abs(J - float(ref["J"])) <= J_REL * abs(float(ref["J"])), (J, float(ref["J"]))
+    nb = float(np.linalg.norm(N(b)))
+    assert abs(nb - ref["norms"][0]) <= 1e-4 * ref["norms"][0], (nb, ref["norms"][0])
 
 
 @pytest.mark.parametrize("precond", ["block", "jacobi", "sgs"])
 def test_c2_precond_apply(c2, precond):
-    v, P, _, _ = c2
+    v, P, _ = c2
     b = 0.5 * v.b_true.reshape(P.L, -1)
     tri = O.hessian_tridiag(P, b, True)
     r = np.random.default_rng(9).normal(size=(P.L, P.M + 1))
     zo = oracle_precond(P, tri, r, precond)
     tol = precond_tol(P, tri, r, precond, zo)
-    with _problem(v, CONFIGS[V128]["alpha"], "mixed") as pr:
+    with _problem(v, V128, "mixed") as pr:
         sh = pr.shape_faces
         z = pr.precond_apply(T(b.reshape(sh)), T(r.reshape(sh)), precond)
         err = np.abs(N(z).reshape(P.L, -1) - zo).max() / np.abs(zo).max()

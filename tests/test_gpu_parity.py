@@ -214,6 +214,90 @@ def test_admm_trajectory(shape, pe, alpha, iters, prec):
             assert ok, (key, msg)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+@pytest.mark.parametrize("rho_mode", ["fixed", "adapt_floor"])
+def test_admm_augmented_lagrangian_history(prec, rho_mode):
+    """with_lagrangian records L_rho(b, z, y) of eq. Lp at every iterate. The oracle
+    evaluates it from its definition (objective terms, transverse differences of z, the
+    multiplier term) at the GPU's own final iterate with the GPU's last rho: relative bar
+    1e-5 (float32 per-cell terms, float64 sums), as for the objective. In float32 the whole
+    history is also compared with the oracle's run at 1e-5 (the split-bfloat16 trajectory
+    drifts from the oracle's by ~1e-5 relative in the objective, see test_gpu_fullsize).
+    Recording the Lagrangian does not change the iteration."""
+    v = generate(3, (40, 36, 24), 2)
+    alpha = 5.0
+    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
+    mode = {"fixed": O.RHO_FIXED, "adapt_floor": O.RHO_ADAPT_FLOOR}[rho_mode]
+    iters = 12
+    bo, zo, uo, ro = O.solve_admm(P, rho=1e3, max_iter=iters, eps_abs=0.0, eps_rel=0.0,
+                                  with_lagrangian=True, rho_mode=mode)
+    with _problem(v, alpha, prec) as pr:
+        b = T(np.zeros(pr.shape_faces))
+        z, u = b.clone(), b.clone()
+        rep = pr.solve_admm(b, z, u, rho=1e3, max_iter=iters, eps_abs=0.0, eps_rel=0.0,
+                            with_lagrangian=1, rho_mode=rho_mode, check_every=5)
+        plain = [T(np.zeros(pr.shape_faces)) for _ in range(3)]
+        pr.solve_admm(*plain, rho=1e3, max_iter=iters, eps_abs=0.0, eps_rel=0.0,
+                      rho_mode=rho_mode, check_every=5)
+    assert rep["iters"] == iters
+    for a, c in zip((b, z, u), plain):
+        np.testing.assert_array_equal(N(a), N(c))
+    Lg = np.asarray(rep["lagrangian"])
+    L_at_gpu = O.augmented_lagrangian(P, P.lines(N(b)), P.lines(N(z)), P.lines(N(u)),
+                                      rep["rho"][-1])
+    assert abs(Lg[-1] - L_at_gpu) <= J_REL * abs(L_at_gpu), (Lg[-1], L_at_gpu)
+    if prec == "fp32":
+        np.testing.assert_allclose(rep["rho"], ro.rho, rtol=1e-12)
+        rel = np.abs(Lg - np.asarray(ro.lagrangian)) / np.abs(np.asarray(ro.lagrangian))
+        assert rel.max() <= J_REL, (int(rel.argmax()), rel.max())
+
+
+def test_admm_augmented_lagrangian_per_iterate():
+    """The Lagrangian recorded for each iterate is the oracle's L_rho at that GPU iterate
+    (one iteration per call; the solve resumes from the state it left)."""
+    v = generate(4, (36, 30, 20), 1)
+    alpha = 2.0
+    P = O.make_problem(v.Ip, v.Im, v.h, alpha)
+    with _problem(v, alpha, "mixed") as pr:
+        b = T(np.zeros(pr.shape_faces))
+        z, u = b.clone(), b.clone()
+        for k in range(8):
+            rep = pr.solve_admm(b, z, u, rho=1e3, max_iter=1, eps_abs=0.0, eps_rel=0.0,
+                                with_lagrangian=1, check_every=1)
+            Lo = O.augmented_lagrangian(P, P.lines(N(b)), P.lines(N(z)), P.lines(N(u)), 1e3)
+            assert abs(rep["lagrangian"][0] - Lo) <= J_REL * abs(Lo), (k, rep["lagrangian"][0], Lo)
+
+
+def test_admm_qp_iteration_cap():
+    """qp_max_iter caps the active-set iterations of one line's QP (eq. qp). On a state
+    with active constraints, a cap of one iteration stops the lines that need more early:
+    the result differs from the uncapped one but stays feasible; a cap above what any line
+    needs reproduces the uncapped result bit for bit."""
+    r = np.random.default_rng(17)
+    M, m2, m3 = 12, 6, 4
+    Ip = 3.0 * r.uniform(0.2, 1.0, size=(m3, m2, M))
+    Im = 3.0 * r.uniform(0.2, 1.0, size=(m3, m2, M))
+    h = (1 / M, 1 / m2, 1 / m3)
+    P = O.make_problem(Ip, Im, h, 0.02)
+    b = _smooth_field(P, 9, 0.7)
+    z = b + 0.3 * P.hp * r.normal(size=b.shape)
+    u = 0.1 * P.hp * r.normal(size=b.shape)
+    from paper_1607_00531_amd import Problem
+    outs = {}
+    with Problem(T(Ip), T(Im), h, 0.02, precision="fp32") as pr:
+        sh = pr.shape_faces
+        for cap in (0, 1, 4 * (M + 1)):
+            bg, zg, ug = T(b.reshape(sh)), T(z.reshape(sh)), T(u.reshape(sh))
+            rep = pr.solve_admm(bg, zg, ug, rho=50.0, max_iter=1, eps_abs=0.0, eps_rel=0.0,
+                                qp_max_iter=cap)
+            assert rep["hard_lines"] > 0
+            outs[cap] = N(bg)
+            gnew = np.diff(outs[cap].reshape(P.L, -1), axis=1) / P.hp
+            assert np.abs(gnew).max() <= 1.0 + 1e-5, cap
+    np.testing.assert_array_equal(outs[0], outs[4 * (M + 1)])
+    assert np.abs(outs[1] - outs[0]).max() > 1e-6 * P.hp
+
+
 def test_admm_stopping_rule_matches_oracle():
     v = config_volume("2d_64x64", 0)
     P = O.make_problem(v.Ip, v.Im, v.h, 50.0)

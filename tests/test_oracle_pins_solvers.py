@@ -333,3 +333,40 @@ def test_admm_stops_exactly_when_both_residuals_meet_their_tolerances():
         assert not (full.r_pri[i] <= rep.eps_pri[i] and full.r_dual[i] <= rep.eps_dual[i])
     assert full.r_pri[k - 1] <= rep.eps_pri[k - 1] and full.r_dual[k - 1] <= rep.eps_dual[k - 1]
     assert all(e >= math.sqrt(n) * 2e-4 for e in rep.eps_pri + rep.eps_dual)
+
+
+# ---------------------------------------------------------------- augmented Lagrangian (eq. Lp)
+def test_augmented_lagrangian_reduces_to_J_and_is_affine_in_the_multiplier():
+    """L_rho(b, z, y) = f(b) + g(z) + y'(b - z) + (rho v / 2)|b - z|^2 (eq. Lp) with
+    f = D + (alpha v / 2)|D1 b|^2 and g = (alpha v / 2)(|D2 z|^2 + |D3 z|^2):
+      * at z = b the multiplier and penalty terms vanish and f + g is J = D + alpha S
+        (the objective without the penalty, itself pinned by finite differences);
+      * it is affine in u with slope rho v (b - z), and a quadratic in rho v at u = 0
+        whose coefficient is |b - z|^2 / 2."""
+    P = rand_problem(11, 6, 5, seed=23, alpha=0.8)
+    r = np.random.default_rng(5)
+    b = smooth_field(P, 4, 0.5)
+    z = b + 0.2 * P.hp * r.normal(size=b.shape)
+    u = 0.3 * P.hp * r.normal(size=b.shape)
+    for rho in (3.0, 40.0):
+        L_bb = O.augmented_lagrangian(P, b, b, u, rho)
+        J = O.objective(P, b, False)["J"]
+        assert math.isclose(L_bb, J, rel_tol=1e-12)
+        L0 = O.augmented_lagrangian(P, b, z, 0.0 * u, rho)
+        L1 = O.augmented_lagrangian(P, b, z, u, rho)
+        L2 = O.augmented_lagrangian(P, b, z, 2.0 * u, rho)
+        slope = rho * P.v * float(np.sum(u * (b - z)))
+        assert math.isclose(L1 - L0, slope, rel_tol=1e-9, abs_tol=1e-15)
+        assert math.isclose(L2 - L1, slope, rel_tol=1e-9, abs_tol=1e-15)
+    # the rho-dependence at u = 0: L(rho) - L(0+) = (rho v / 2)|b - z|^2
+    La = O.augmented_lagrangian(P, b, z, 0.0 * u, 1e-12)
+    Lb = O.augmented_lagrangian(P, b, z, 0.0 * u, 10.0)
+    assert math.isclose(Lb - La, 0.5 * 10.0 * P.v * float(np.sum((b - z) ** 2)), rel_tol=1e-9)
+    # g(z) alone: with b = z the part that depends on z only is alpha v / 2 of the
+    # transverse differences, i.e. J(z) minus D(z) minus the D1 part
+    S = O.objective(P, z, False)
+    d1 = np.diff(P.lines(z), axis=1) / P.hp
+    g_z = P.alpha * S["S"] - 0.5 * P.alpha * P.v * float(np.sum(d1 * d1))
+    L_zz = O.augmented_lagrangian(P, z, z, u, 5.0)
+    f_z = S["D"] + 0.5 * P.alpha * P.v * float(np.sum(d1 * d1))
+    assert math.isclose(L_zz, f_z + g_z, rel_tol=1e-12)
