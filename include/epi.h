@@ -194,6 +194,27 @@ void epi_admm_default_opts(epi_admm_opts* opts);
 epi_status epi_setup(const epi_grid* grid, const float* d_Iplus, const float* d_Iminus,
                      void* stream, epi_problem** out);
 
+/* Bytes of the static device scratch of epi_objective_noalloc: float64 partial sums, 48
+ * bytes per four PE lines, so at most 43,688 PE lines (m2 m3) per call (240 x 200 x 110
+ * with the PE axis first has 22,000). */
+#define EPI_NOALLOC_SCRATCH_BYTES (1 << 19)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the objective terms of epi_objective
+ * without a problem handle and without any device allocation. grid, images and field as
+ * for epi_setup and epi_objective (device pointers, canonical layout, caller-owned).
+ * d_terms: caller-owned device array of 5 doubles that receives J, D, S, P and the
+ * feasibility flag (1.0 iff every |D1 b| < 1; P = +inf otherwise when with_penalty != 0).
+ * d_grad: NULL or n floats for grad J / grad J_GN. Everything is enqueued on stream
+ * (a hipStream_t or NULL) and the call returns without synchronising. The partial sums
+ * live in a static device array of EPI_NOALLOC_SCRATCH_BYTES per GPU, held until the
+ * process ends; its address is looked up once per device. Calls that overlap on one GPU
+ * (several streams or host threads) share that array and race. EPI_EINVAL for a grid
+ * whose line count exceeds the scratch. The images are not checked for NaN/Inf. */
+epi_status epi_objective_noalloc(const epi_grid* grid, const float* d_Iplus,
+                                 const float* d_Iminus, const float* d_b, int32_t with_penalty,
+                                 double* d_terms, float* d_grad, void* stream);
+
 /* Quality of a field estimate: the SSD distance D of the corrected pair (eq. D), the
  * normalised cross-correlation of the two corrected images and their means. */
 typedef struct {

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libepi.so")
 OBJDIR = os.path.join(ROOT, "_build", "epi")
 SOURCES = ["epi_api.hip", "epi_line.hip", "epi_vec.hip", "epi_dct.hip", "epi_batch.hip",
-           "epi_serve.hip", "epi_multilevel.hip"]
+           "epi_serve.hip", "epi_multilevel.hip", "epi_noalloc.hip"]
 
 
 def hipcc() -> str:

@@ -84,7 +84,8 @@ enum FinKind : int {
   FIN_LS_INIT = 8,     // J0 = value; clear the line-search state
   FIN_HARD_RESET = 9,  // fold hard_count into hard_total between SQP linearisations
   FIN_QUALITY = 10,    // -> st->quality (sums of the corrected-image pair)
-  FIN_LAGRANGIAN = 11  // augmented Lagrangian of the last ADMM iterate -> history row 5
+  FIN_LAGRANGIAN = 11, // augmented Lagrangian of the last ADMM iterate -> history row 5
+  FIN_TERMS = 12       // objective terms J, D, S, P, feasible -> hist[0..4] (trial: penalty)
 };
 struct FinArgs {
   int kind;

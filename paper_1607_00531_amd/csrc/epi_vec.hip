@@ -323,6 +323,20 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f, DevState* st) {
         st->lagr_last = st->admm_iter;
       }
     } break;
+    case FIN_TERMS: {
+      reduce_partials<NQ_EVAL>(f.partial, f.nb1, s);
+      if (threadIdx.x == 0) {
+        const double D = 0.5 * f.v * s[0];
+        const double S = 0.5 * f.v * (s[1] + s[2]);
+        const bool feasible = s[4] == 0.0;
+        const double P = f.trial ? (feasible ? f.beta * f.v * s[3] : INFINITY) : 0.0;
+        f.hist[0] = D + f.alpha * S + P;
+        f.hist[1] = D;
+        f.hist[2] = S;
+        f.hist[3] = P;
+        f.hist[4] = feasible ? 1.0 : 0.0;
+      }
+    } break;
     case FIN_HARD_RESET: {
       if (threadIdx.x == 0 && !st->admm_done) {
         st->hard_total += st->hard_count;
