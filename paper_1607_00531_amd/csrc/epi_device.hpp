@@ -494,5 +494,16 @@ __device__ __forceinline__ float d2phi_f(float x) {
   const float x2 = x * x;
   return 2.0f * x2 * (x2 * x2 - 3.0f * x2 + 6.0f) / (q * q * q);
 }
+// phi, phi' and phi'' together with one hardware reciprocal of q = 1 - x^2 (1 ulp) instead
+// of three divisions.
+__device__ __forceinline__ void phi_terms(float x, float& ph, float& d1, float& d2) {
+  const float q = (1.0f - x) * (1.0f + x);
+  const float iq = rcp_f(q);
+  const float x2 = x * x;
+  const float iq2 = iq * iq;
+  ph = x2 * x2 * iq;
+  d1 = (4.0f - 2.0f * x2) * x2 * x * iq2;
+  d2 = 2.0f * x2 * (x2 * x2 - 3.0f * x2 + 6.0f) * iq2 * iq;
+}
 
 }  // namespace epi

@@ -25,7 +25,9 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
                                                float* __restrict__ hoff, double* partial,
                                                const DevState* st) {
   if (dsrc != nullptr && st->ls_done) return;
-  __shared__ float sbuf[EPI_LINE_WAVES][7][LineBuf<P>::SIZE];
+  // per wave: the two image lines, its own field line (read by the neighbouring waves too),
+  // the k - 1 and k + 1 lines and, for the workgroup's end waves, the outer j neighbour
+  __shared__ float sbuf[EPI_LINE_WAVES][6][LineBuf<P>::SIZE];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = xcd_remap(blockIdx.x, a.nblk);
   const int line = blk * EPI_LINE_WAVES + wave;
@@ -34,42 +36,58 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
   const int jj = lc % a.m2, kk = lc / a.m2;
   const int NF = a.M + 1;
   const float lam = (dsrc != nullptr) ? ldexpf(1.0f, -trial) : 0.0f;
-
+  const bool j0 = jj > 0, j1 = jj < a.m2 - 1, k0 = kk > 0, k1 = kk < a.m3 - 1;
+  const bool jm_lds = j0 && wave > 0, jp_lds = j1 && wave < EPI_LINE_WAVES - 1;
+  const int jo = (wave == 0) ? lc - 1 : lc + 1;
+  const bool jo_need = (wave == 0) ? j0 : (wave == EPI_LINE_WAVES - 1 ? j1 : false);
   float* sIp = sbuf[wave][0];
   float* sIm = sbuf[wave][1];
-  for (int t = lane; t < 64 * P; t += 64) {
-    sIp[lds_pad(t)] = (valid && t < a.M) ? a.Ip[(size_t)lc * a.M + t] : 0.0f;
-    sIm[lds_pad(t)] = (valid && t < a.M) ? a.Im[(size_t)lc * a.M + t] : 0.0f;
-  }
-  float b[P], nb[4][P];
+  float b[P], nb[4][P];   // nb: j - 1, j + 1, k - 1, k + 1 (a missing neighbour: b itself)
   {
-    // the line and its transverse neighbours (j-1, j+1, k-1, k+1) in one memory round trip
-    // (a second one for the search direction d); a missing neighbour gets a copy of b
-    const int nl[4] = {jj > 0 ? lc - 1 : -1, jj < a.m2 - 1 ? lc + 1 : -1,
-                       kk > 0 ? lc - a.m2 : -1, kk < a.m3 - 1 ? lc + a.m2 : -1};
-    const float* srcs[5];
-    const int cnt[5] = {NF, NF, NF, NF, NF};
-    srcs[0] = bsrc + (size_t)lc * NF;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) srcs[1 + q] = bsrc + (size_t)(nl[q] >= 0 ? nl[q] : lc) * NF;
-    float v[5][P];
-    stage_in_n<P, 5>(srcs, cnt, valid, &sbuf[wave][2][0], v, lane);
+    // every global load of the wavefront in one round trip (a second one for d)
+    const float* srcs[6] = {a.Ip + (size_t)lc * a.M, a.Im + (size_t)lc * a.M,
+                            bsrc + (size_t)lc * NF,
+                            bsrc + (size_t)(k0 ? lc - a.m2 : lc) * NF,
+                            bsrc + (size_t)(k1 ? lc + a.m2 : lc) * NF,
+                            bsrc + (size_t)(jo_need ? jo : lc) * NF};
+    const int cnt[6] = {a.M, a.M, NF, NF, NF, NF};
+    float v[6][P];
+    load_line_n<P, 6>(srcs, cnt, valid, v, lane);
     if (dsrc != nullptr) {
+      const float* dsr[4];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) srcs[q] = dsrc + (srcs[q] - bsrc);
-      float w[5][P];
-      stage_in_n<P, 5>(srcs, cnt, valid, &sbuf[wave][2][0], w, lane);
+      for (int q = 0; q < 4; ++q) dsr[q] = dsrc + (srcs[2 + q] - bsrc);
+      const int dc[4] = {NF, NF, NF, NF};
+      float w[4][P];
+      load_line_n<P, 4>(dsr, dc, valid, w, lane);
 #pragma unroll
-      for (int q = 0; q < 5; ++q)
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int j = 0; j < P; ++j) v[q][j] = fmaf(lam, w[q][j], v[q][j]);
+        for (int j = 0; j < P; ++j) v[2 + q][j] = fmaf(lam, w[q][j], v[2 + q][j]);
     }
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int j = 0; j < P; ++j) sbuf[wave][q][lds_pad(lane + 64 * j)] = v[q][j];
+    __syncthreads();
+    const float* own = sbuf[wave][2];
+    const float* jm = jm_lds ? sbuf[wave - 1][2] : (wave == 0 && j0 ? sbuf[wave][5] : own);
+    const float* jp = jp_lds ? sbuf[wave + 1][2]
+                             : (wave == EPI_LINE_WAVES - 1 && j1 ? sbuf[wave][5] : own);
+    const float* km = k0 ? sbuf[wave][3] : own;
+    const float* kp = k1 ? sbuf[wave][4] : own;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      b[j] = v[0][j];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) nb[q][j] = (nl[q] >= 0) ? v[1 + q][j] : v[0][j];
+      const int t = lds_pad(P * lane + j);
+      b[j] = own[t];
+      nb[0][j] = jm[t];
+      nb[1][j] = jp[t];
+      nb[2][j] = km[t];
+      nb[3][j] = kp[t];
     }
+    // the field lines are read by other waves only before this barrier; after it each wave
+    // reuses its own buffers 3..5 for the output staging
+    __syncthreads();
   }
 
   Cells<P> C;
@@ -88,9 +106,11 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
       const float x = C.g[j];
       if (fabsf(x) < 1.0f) {
         if (with_pen) {
-          acc[3] += (double)phi_f(x);
-          phid[j] = dphi_f(x);
-          phidd[j] = d2phi_f(x);
+          float ph, d1, d2;
+          phi_terms(x, ph, d1, d2);
+          acc[3] += (double)ph;
+          phid[j] = d1;
+          phidd[j] = d2;
         }
       } else {
         acc[4] += 1.0;
@@ -112,7 +132,7 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
     prev_cell<P>(C.g, gprev, lane);
     prev_cell<P>(phid, phdprev, lane);
     const float av = a.alpha * a.v;
-    float gout[P];
+    float out[3][P];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const int i = P * lane + j;
@@ -122,35 +142,34 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
       lap += ((b[j] - nb[2][j]) + (b[j] - nb[3][j])) * a.inv_h3sq;
       gv += av * lap;
       if (with_pen) gv += a.beta * a.v * (phdprev[j] - phid[j]) * a.inv_hp;
-      gout[j] = (i < NF) ? gv : 0.0f;
+      out[0][j] = (i < NF) ? gv : 0.0f;
       if (valid && i < NF) acc[5] += (double)gv * gv;
     }
-    if (grad != nullptr) stage_out<P>(grad + (size_t)lc * NF, NF, valid, sbuf[wave][2], gout, lane);
-  }
-
-  if (MODE == 2) {
-    float JrPrev[P], phddPrev[P];
-    prev_cell<P>(C.Jr, JrPrev, lane);
-    prev_cell<P>(phidd, phddPrev, lane);
-    const float qa = a.alpha * a.v * a.inv_hp * a.inv_hp;
-    const float qb = a.beta * a.v * a.inv_hp * a.inv_hp;
-    float dg[P], of[P];
+    if (MODE == 2) {
+      float JrPrev[P], phddPrev[P];
+      prev_cell<P>(C.Jr, JrPrev, lane);
+      prev_cell<P>(phidd, phddPrev, lane);
+      const float qa = a.alpha * a.v * a.inv_hp * a.inv_hp;
+      const float qb = a.beta * a.v * a.inv_hp * a.inv_hp;
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int i = P * lane + j;
-      const float ncell = (float)((i < a.M) + (i >= 1 && i <= a.M));
-      float dgv = a.v * (C.Jl[j] * C.Jl[j] + JrPrev[j] * JrPrev[j]) + qa * ncell + a.gamma;
-      float ofv = 0.0f;
-      if (i < a.M) ofv = a.v * C.Jl[j] * C.Jr[j] - qa;
-      if (with_pen) {
-        dgv += qb * (phidd[j] + phddPrev[j]);
-        if (i < a.M) ofv -= qb * phidd[j];
+      for (int j = 0; j < P; ++j) {
+        const int i = P * lane + j;
+        const float ncell = (float)((i < a.M) + (i >= 1 && i <= a.M));
+        float dgv = a.v * (C.Jl[j] * C.Jl[j] + JrPrev[j] * JrPrev[j]) + qa * ncell + a.gamma;
+        float ofv = 0.0f;
+        if (i < a.M) ofv = a.v * C.Jl[j] * C.Jr[j] - qa;
+        if (with_pen) {
+          dgv += qb * (phidd[j] + phddPrev[j]);
+          if (i < a.M) ofv -= qb * phidd[j];
+        }
+        out[1][j] = (i < NF) ? dgv : 1.0f;
+        out[2][j] = ofv;
       }
-      dg[j] = (i < NF) ? dgv : 1.0f;
-      of[j] = ofv;
+      float* dst[3] = {grad + (size_t)lc * NF, hdiag + (size_t)lc * NF, hoff + (size_t)lc * NF};
+      stage_out_n<P, 3>(dst, NF, valid, sbuf[wave][3], out, lane);
+    } else if (grad != nullptr) {
+      stage_out<P>(grad + (size_t)lc * NF, NF, valid, sbuf[wave][3], out[0], lane);
     }
-    stage_out<P>(hdiag + (size_t)lc * NF, NF, valid, sbuf[wave][2], dg, lane);
-    stage_out<P>(hoff + (size_t)lc * NF, NF, valid, sbuf[wave][2], of, lane);
   }
   block_partials<NQ_EVAL>(acc, partial, blockIdx.x);
 }

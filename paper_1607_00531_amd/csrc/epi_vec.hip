@@ -29,7 +29,9 @@ __device__ __forceinline__ void chunk_of(long long n, long long& lo, long long& 
 // neighbours along the line come from lane shifts. The four wavefronts of a workgroup hold
 // four consecutive lines and share them through LDS, so the j +- 1 neighbours of the inner
 // lines are read there; the other neighbour lines (j +- 1 at the workgroup's ends, k +- 1)
-// come from L2.
+// come from L2. Every global load of a wavefront (its line, the k +- 1 lines and, at the
+// workgroup's ends, the outer j neighbour) is issued before the first arithmetic, from
+// clamped (always valid) line indices, and missing neighbours are selected away after.
 // DIR: the PCG direction update is fused in: p = z + beta p_old is formed on the fly at
 // every stencil point (the same value the separate update computes), written to pnew, and
 // q = H p; otherwise p = pold.
@@ -55,26 +57,43 @@ __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restr
   const int NF = a.M + 1;
   const int jj = lc % a.m2, kk = lc / a.m2;
   const size_t base = (size_t)lc * NF;
-  const int plane = NF * a.m2;
-  const float* pl = pold + base;
-  const float* zl = DIR ? z + base : nullptr;
-  const auto pat = [&](int o) { return DIR ? fmaf(be, pl[o], zl[o]) : pl[o]; };
   const float av = a.alpha * a.v;
   const bool j0 = jj > 0, j1 = jj < a.m2 - 1, k0 = kk > 0, k1 = kk < a.m3 - 1;
-  float pc[P], hdv[P], hov[P];
+  // the j neighbours from LDS when they belong to this workgroup's lines
+  const bool jm_lds = j0 && wave > 0, jp_lds = j1 && wave < EPI_LINE_WAVES - 1;
+  // lines read from global: 0 own, 1 k - 1, 2 k + 1, 3 the outer j neighbour of an end wave
+  const int jo = (wave == 0) ? lc - 1 : lc + 1;
+  const bool jo_need = (wave == 0) ? j0 : (wave == EPI_LINE_WAVES - 1 ? j1 : false);
+  const int lines[4] = {lc, k0 ? lc - a.m2 : lc, k1 ? lc + a.m2 : lc, jo_need ? jo : lc};
+  float pv[4][P], zv[4][P], hdv[P], hov[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int i = lane + 64 * j;
+    const int ic = (j < P - 1 || i < NF) ? i : NF - 1;   // in bounds; replaced below
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const size_t o = (size_t)lines[t] * NF + ic;
+      pv[t][j] = pold[o];
+      if (DIR) zv[t][j] = z[o];
+    }
+    hdv[j] = hd[base + ic];
+    hov[j] = ho[base + ic];
+  }
+  float pc[P], pk0[P], pk1[P], pjo[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int i = lane + 64 * j;
     const bool ok = lv && (j < P - 1 || i < NF);
-    pc[j] = ok ? pat(i) : 0.0f;
+    const auto mk = [&](int t) { return DIR ? fmaf(be, pv[t][j], zv[t][j]) : pv[t][j]; };
+    pc[j] = ok ? mk(0) : 0.0f;
+    pk0[j] = mk(1);
+    pk1[j] = mk(2);
+    pjo[j] = mk(3);
     sp[wave][i] = pc[j];
-    hdv[j] = ok ? hd[base + i] : 0.0f;
-    hov[j] = ok ? ho[base + i] : 0.0f;
   }
   __syncthreads();
-  // line - 1 / line + 1 of this workgroup (the same k-plane whenever the neighbour exists)
-  const float* spm = wave > 0 ? sp[wave - 1] : nullptr;
-  const float* spp = wave < EPI_LINE_WAVES - 1 ? sp[wave + 1] : nullptr;
+  const float* spm = jm_lds ? sp[wave - 1] : nullptr;
+  const float* spp = jp_lds ? sp[wave + 1] : nullptr;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int i = lane + 64 * j;
@@ -92,16 +111,16 @@ __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restr
       if (lane == 63) pn = e2;
     }
     const bool ok = lv && (j < P - 1 || i < NF);
+    float y = hdv[j] * pc[j];
+    if (i > 0) y = fmaf(ho_p, pp, y);
+    if (i < NF - 1) y = fmaf(hov[j], pn, y);
+    float l2 = 0.0f, l3 = 0.0f;
+    if (j0) l2 += pc[j] - (spm ? spm[i] : pjo[j]);
+    if (j1) l2 += pc[j] - (spp ? spp[i] : pjo[j]);
+    if (k0) l3 += pc[j] - pk0[j];
+    if (k1) l3 += pc[j] - pk1[j];
+    y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
     if (ok) {
-      float y = hdv[j] * pc[j];
-      if (i > 0) y = fmaf(ho_p, pp, y);
-      if (i < NF - 1) y = fmaf(hov[j], pn, y);
-      float l2 = 0.0f, l3 = 0.0f;
-      if (j0) l2 += pc[j] - (spm ? spm[i] : pat(i - NF));
-      if (j1) l2 += pc[j] - (spp ? spp[i] : pat(i + NF));
-      if (k0) l3 += pc[j] - pat(i - plane);
-      if (k1) l3 += pc[j] - pat(i + plane);
-      y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
       if (DIR) store_stream(&pnew[base + i], pc[j]);
       store_stream(&q[base + i], y);
       acc[0] += (double)pc[j] * y;
