@@ -51,6 +51,8 @@ __all__ = [
     "solve_multilevel_admm", "solve_multilevel_gnpcg", "ml_restart",
     "ML_RESTART_PROLONG_ALL", "ML_RESTART_FINE_B", "ML_RESTART_AVERAGE",
     "dense_operators",
+    "bspline3", "bspline3_d1", "bspline3_d2", "spline_collocation", "spline_curvature_gram",
+    "spline_coefficients", "interp_spline", "set_image_model",
 ]
 
 
@@ -70,6 +72,12 @@ class Problem:
     alpha: float
     beta: float = 10.0
     gamma: float = 1e-3
+    # image model: "linear" (Section 3) or "spline" (the smoothed cubic B-spline model of the
+    # comparison in Section 5) with smoothing weight theta and coefficients Wp, Wm (L, M)
+    model: str = "linear"
+    theta: float = 0.0
+    Wp: Optional[np.ndarray] = None
+    Wm: Optional[np.ndarray] = None
 
     @property
     def L(self) -> int:
@@ -128,6 +136,118 @@ def interp_linear(T: np.ndarray, s: np.ndarray, hp: float):
     return val, der
 
 
+# ---------------------------------------------------------------------------------------
+# Smoothed cubic B-spline image model (Section 5: the default of the comparison method,
+# whose definition the paper leaves to the image-registration literature). Readings:
+#   * the model is one-dimensional along PE, per line, like the linear one;
+#   * I(s) = sum_k w_k beta3(s - k) in index units (sample c at s = c), coefficients on
+#     the M sample positions and zero outside them (compact support, as for the linear
+#     model), so I vanishes for s <= -2 and s >= M + 1;
+#   * w minimises |B w - T|^2 + theta w' G w with B the collocation matrix at the samples
+#     (B[c, k] = beta3(c - k)) and G the Gram matrix of the second derivatives
+#     (G[k, l] = integral of beta3''(s - k) beta3''(s - l) ds), so w solves
+#     (B'B + theta G) w = B'T; theta = 0 is plain spline interpolation, B w = T;
+#   * I'(x) = sum_k w_k beta3'(s - k) / h_p.
+# ---------------------------------------------------------------------------------------
+def bspline3(t):
+    """Cubic B-spline: 2/3 - t^2 + |t|^3 / 2 on |t| < 1, (2 - |t|)^3 / 6 on 1 <= |t| < 2."""
+    a = np.abs(t)
+    return np.where(a < 1.0, 2.0 / 3.0 - a * a + 0.5 * a ** 3,
+                    np.where(a < 2.0, (2.0 - a) ** 3 / 6.0, 0.0))
+
+
+def bspline3_d1(t):
+    """First derivative of bspline3."""
+    a = np.abs(t)
+    sg = np.sign(t)
+    return np.where(a < 1.0, -2.0 * t + 1.5 * t * a, np.where(a < 2.0, -0.5 * sg * (2.0 - a) ** 2, 0.0))
+
+
+def bspline3_d2(t):
+    """Second derivative of bspline3 (piecewise linear)."""
+    a = np.abs(t)
+    return np.where(a < 1.0, -2.0 + 3.0 * a, np.where(a < 2.0, 2.0 - a, 0.0))
+
+
+def spline_collocation(M: int) -> np.ndarray:
+    """B[c, k] = beta3(c - k) for samples and coefficients 0..M-1 (dense, for clarity)."""
+    c = np.arange(M, dtype=np.float64)
+    return bspline3(c[:, None] - c[None, :])
+
+
+def spline_curvature_gram(M: int) -> np.ndarray:
+    """G[k, l] = integral over the real line of beta3''(s - k) beta3''(s - l) ds. beta3''
+    is linear on every unit interval, so Simpson's rule on each interval is exact."""
+    G = np.zeros((M, M))
+    for d in range(4):
+        m = np.arange(-2, 2)          # the intervals [m, m + 1] that can carry both supports
+        lo, mid, hi = m.astype(float), m + 0.5, m + 1.0
+        f = lambda x: bspline3_d2(x) * bspline3_d2(x - d)
+        val = float(np.sum((f(lo) + 4.0 * f(mid) + f(hi)) / 6.0))
+        idx = np.arange(M - d)
+        G[idx, idx + d] = val
+        G[idx + d, idx] = val
+    return G
+
+
+def spline_coefficients(T: np.ndarray, theta: float) -> np.ndarray:
+    """Coefficients w (rows = lines) of the smoothed fit to the samples T."""
+    import scipy.linalg as sla
+    L_, M = T.shape
+    B = spline_collocation(M)
+    if theta == 0.0:
+        ab = np.zeros((3, M))
+        ab[0, 1:] = np.diag(B, 1)
+        ab[1] = np.diag(B)
+        ab[2, :-1] = np.diag(B, -1)
+        return sla.solve_banded((1, 1), ab, T.T).T
+    A = B.T @ B + theta * spline_curvature_gram(M)
+    ab = np.zeros((4, M))            # upper form of a symmetric band of half-width 3
+    for d in range(4):
+        ab[3 - d, d:] = np.diag(A, d)
+    return sla.solveh_banded(ab, (T @ B).T).T
+
+
+def interp_spline(W: np.ndarray, s: np.ndarray, hp: float):
+    """Value and physical derivative of the spline with coefficients W (rows = lines) at
+    index coordinates s: the four coefficients k - 1 .. k + 2 around k = floor(s)."""
+    Lr, M = W.shape
+    Wp = np.zeros((Lr, M + 6))
+    Wp[:, 3:M + 3] = W                 # column of coefficient k: k + 3
+    k = np.floor(s)
+    f = s - k
+    inside = (k >= -3) & (k <= M + 1)
+    ki = np.where(inside, k, -3).astype(np.int64)
+    rows = np.arange(Lr)[:, None]
+    val = np.zeros_like(s)
+    der = np.zeros_like(s)
+    for i in range(-1, 3):
+        col = np.clip(ki + i + 3, 0, M + 5)
+        w = Wp[rows, col]
+        val = val + w * bspline3(f - i)
+        der = der + w * bspline3_d1(f - i)
+    return np.where(inside, val, 0.0), np.where(inside, der / hp, 0.0)
+
+
+def set_image_model(P: Problem, model: str, theta: float = 0.0) -> Problem:
+    """Switch P to the linear or the smoothed cubic-spline image model (in place)."""
+    if model == "linear":
+        P.model, P.theta, P.Wp, P.Wm = "linear", 0.0, None, None
+    elif model == "spline":
+        P.model, P.theta = "spline", float(theta)
+        P.Wp = spline_coefficients(P.Ip, P.theta)
+        P.Wm = spline_coefficients(P.Im, P.theta)
+    else:
+        raise ValueError(f"unknown image model {model!r}")
+    return P
+
+
+def _interp(P: Problem, which: str, s: np.ndarray):
+    if P.model == "spline":
+        return interp_spline(P.Wp if which == "+" else P.Wm, s, P.hp)
+    return interp_linear(P.Ip if which == "+" else P.Im, s, P.hp)
+
+
 def line_eval(P: Problem, b: np.ndarray) -> Dict[str, np.ndarray]:
     """Per-cell quantities of the distance term at b (faces, any shape with n entries).
 
@@ -141,8 +261,8 @@ def line_eval(P: Problem, b: np.ndarray) -> Dict[str, np.ndarray]:
     a = 0.5 * (bl[:, :-1] + bl[:, 1:])
     g = (bl[:, 1:] - bl[:, :-1]) / P.hp
     c = np.arange(P.M, dtype=np.float64)[None, :]
-    ipv, ipd = interp_linear(P.Ip, c + a / P.hp, P.hp)
-    imv, imd = interp_linear(P.Im, c - a / P.hp, P.hp)
+    ipv, ipd = _interp(P, "+", c + a / P.hp)
+    imv, imd = _interp(P, "-", c - a / P.hp)
     r = ipv * (1.0 + g) - imv * (1.0 - g)
     Sd = ipd * (1.0 + g) + imd * (1.0 - g)
     Tv = ipv + imv
@@ -695,6 +815,8 @@ def _qp_data(P: Problem, bl, zl, ul, rho):
 def bstep_line(P: Problem, bl, zl, ul, ip, im, rho, tol=1e-12):
     """The QP of one PE line (QP data at b^k, then :func:`qp_active_set`)."""
     sub = Problem(ip[None], im[None], P.M, 1, 1, P.hp, P.h2, P.h3, P.alpha, P.beta, P.gamma)
+    if P.model != "linear":
+        set_image_model(sub, P.model, P.theta)   # line-local fit, the same as P's row
     Gd, Go, c, g = _qp_data(sub, bl[None], zl[None], ul[None], rho)
     return qp_active_set(Gd[0], Go[0], c[0], g[0], P.hp, tol)
 
