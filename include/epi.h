@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define EPI_ABI_VERSION 5
+#define EPI_ABI_VERSION 6
 
 typedef enum {
   EPI_OK = 0,
@@ -72,10 +72,21 @@ typedef enum {
   EPI_PRECOND_SGS = 3
 } epi_precond;
 
+/* Continuous model of each image along the phase-encoding axis (Section 3 discretises with
+ * linear interpolation; Section 5 compares against a smoothed cubic B-spline model).
+ * LINEAR: I(s) interpolates the cell-centred samples linearly, zero outside the volume.
+ * SPLINE: I(s) = sum_k w_k beta3(s - k) over the line's M cell centres (zero coefficients
+ * outside), with w the solution of (B'B + theta G) w = B' T per PE line, B the collocation
+ * matrix of beta3 at the samples and G the Gram matrix of the second derivatives
+ * (theta = 0: B w = T, interpolation). The coefficients are computed once at setup. */
+typedef enum { EPI_IMAGE_LINEAR = 0, EPI_IMAGE_SPLINE = 1 } epi_image_model;
+
 /* Problem geometry and weights (Section 3). h = voxel edges (h[2] = 1 in 2D); the cell
  * volume v = h[0] h[1] h[2] plays the role of the paper's h^3. alpha weights the
  * smoothness regulariser S, beta the penalty P (default 10), gamma the identity shift of
- * the approximate Hessians (default 1e-3, unscaled). */
+ * the approximate Hessians (default 1e-3, unscaled). image_model (epi_image_model,
+ * default LINEAR) and theta (>= 0, the smoothing weight of the SPLINE model in grid units,
+ * default 0) select the image model; the batched engine takes LINEAR only. */
 typedef struct {
   int32_t ndim;
   int32_t m[3];
@@ -83,7 +94,9 @@ typedef struct {
   double alpha;
   double beta;
   double gamma;
-  int32_t precision; /* epi_precision */
+  int32_t precision;   /* epi_precision */
+  int32_t image_model; /* epi_image_model */
+  double theta;
 } epi_grid;
 
 /* Objective terms at a field b: J = D + alpha S (+ P when the penalty is requested).
@@ -210,7 +223,8 @@ epi_status epi_setup(const epi_grid* grid, const float* d_Iplus, const float* d_
  * live in a static device array of EPI_NOALLOC_SCRATCH_BYTES per GPU, held until the
  * process ends; its address is looked up once per device. Calls that overlap on one GPU
  * (several streams or host threads) share that array and race. EPI_EINVAL for a grid
- * whose line count exceeds the scratch. The images are not checked for NaN/Inf. */
+ * whose line count exceeds the scratch; EPI_ENOTSUP for the SPLINE image model (its
+ * coefficients come from epi_setup). The images are not checked for NaN/Inf. */
 epi_status epi_objective_noalloc(const epi_grid* grid, const float* d_Iplus,
                                  const float* d_Iminus, const float* d_b, int32_t with_penalty,
                                  double* d_terms, float* d_grad, void* stream);

@@ -1061,8 +1061,9 @@ def ml_restart(P: Problem, strategy: int, bc, zc, uc, mc, mf):
     raise ValueError(strategy)
 
 
-def _ml_problems(Ip, Im, h, alpha, levels, beta, gamma):
-    """(sizes coarse to fine, a function level -> Problem on that level's restricted images)."""
+def _ml_problems(Ip, Im, h, alpha, levels, beta, gamma, image_model="linear", theta=0.0):
+    """(sizes coarse to fine, a function level -> Problem on that level's restricted images;
+    every level uses the same image model, the spline one fitted to that level's images)."""
     M, m2, m3 = Ip.shape[2], Ip.shape[1], Ip.shape[0]
     sizes = level_sizes(M, m2, m3, levels)
     imgs = {sizes[-1]: (np.asarray(Ip, np.float64), np.asarray(Im, np.float64))}
@@ -1075,18 +1076,19 @@ def _ml_problems(Ip, Im, h, alpha, levels, beta, gamma):
         hl = tuple(h[a] * (M, m2, m3)[a] / sz[a] for a in range(3))
         if m3 == 1:
             hl = (hl[0], hl[1], h[2])
-        return make_problem(imgs[sz][0], imgs[sz][1], hl, alpha, beta, gamma)
+        P = make_problem(imgs[sz][0], imgs[sz][1], hl, alpha, beta, gamma)
+        return set_image_model(P, image_model, theta)
 
     return sizes, problem
 
 
 def solve_multilevel_admm(Ip, Im, h, alpha, levels=3, beta=10.0, gamma=1e-3, rho=1e3,
-                          restart=ML_RESTART_AVERAGE, **admm):
+                          restart=ML_RESTART_AVERAGE, image_model="linear", theta=0.0, **admm):
     """Coarse-to-fine ADMM (Section 4.4) from b = z = u = 0 on the coarsest level, the
     finer levels started by ml_restart (the paper's experiments use strategy 3). rho carries
     over between levels (the rho of the last iteration). Returns (b on the finest grid,
     per-level ADMM reports, sizes)."""
-    sizes, problem = _ml_problems(Ip, Im, h, alpha, levels, beta, gamma)
+    sizes, problem = _ml_problems(Ip, Im, h, alpha, levels, beta, gamma, image_model, theta)
     reps = []
     bc = zc = uc = None
     for li, sz in enumerate(sizes):
@@ -1102,12 +1104,13 @@ def solve_multilevel_admm(Ip, Im, h, alpha, levels=3, beta=10.0, gamma=1e-3, rho
     return bc, reps, sizes
 
 
-def solve_multilevel_gnpcg(Ip, Im, h, alpha, levels=3, beta=10.0, gamma=1e-3, **gn):
+def solve_multilevel_gnpcg(Ip, Im, h, alpha, levels=3, beta=10.0, gamma=1e-3, image_model="linear",
+                           theta=0.0, **gn):
     """Coarse-to-fine GN-PCG (Section 4.4): GN from b = 0 on the coarsest level, each finer
     level started from the prolongation of the coarser result (feasible: prolongation keeps
     the coarse D1 b values along PE and mixes lines convexly across). Returns (b on the
     finest grid, per-level GN reports, sizes)."""
-    sizes, problem = _ml_problems(Ip, Im, h, alpha, levels, beta, gamma)
+    sizes, problem = _ml_problems(Ip, Im, h, alpha, levels, beta, gamma, image_model, theta)
     reps = []
     bc = None
     for li, sz in enumerate(sizes):

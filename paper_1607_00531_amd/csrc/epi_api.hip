@@ -62,6 +62,7 @@ struct epi_problem {
   double v;
   const float* Ip;
   const float* Im;
+  float *wp = nullptr, *wm = nullptr;   // spline coefficients of Ip, Im (image_model 1)
   hipStream_t user = nullptr;
   hipStream_t exec = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -342,7 +343,7 @@ EPI_API void epi_destroy(epi_problem* p) {
   if (p->exec) (void)hipStreamSynchronize(p->exec);
   free_graph(p);
   void* bufs[] = {p->w, p->t1, p->t2, p->g, p->hd, p->ho, p->x, p->r, p->zz, p->p, p->q,
-                  p->partial, p->partial_e, p->st, p->hard_list, p->hist};
+                  p->partial, p->partial_e, p->st, p->hard_list, p->hist, p->wp, p->wm};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   free_dct_tables(&p->tab);
@@ -375,7 +376,46 @@ epi_status epi::validate_grid(const epi_grid* grid) {
     return fail(EPI_EINVAL, "alpha, beta, gamma must be >= 0");
   if (grid->precision != EPI_PREC_FP32 && grid->precision != EPI_PREC_MIXED)
     return fail(EPI_EINVAL, "unknown precision %d", grid->precision);
+  if (grid->image_model != EPI_IMAGE_LINEAR && grid->image_model != EPI_IMAGE_SPLINE)
+    return fail(EPI_EINVAL, "unknown image model %d", grid->image_model);
+  if (!(grid->theta >= 0.0)) return fail(EPI_EINVAL, "theta must be >= 0");
   return EPI_OK;
+}
+
+// The line system of the cubic B-spline coefficients, factored as L D L' in float64 (band
+// half-width 3). theta = 0: the collocation matrix B itself, B[c][k] = beta3(c - k) with
+// beta3(0) = 2/3, beta3(+-1) = 1/6 (interpolation). theta > 0: B'B + theta G, with
+// (B'B)[k][k] = 1/2 (17/36 at the two end coefficients, which miss a neighbouring sample),
+// (B'B)[k][k+1] = 2/9, (B'B)[k][k+2] = 1/36, and G the Gram matrix of the second
+// derivatives, integral beta3''(s - k) beta3''(s - l) ds = 8/3, -3/2, 0, 1/6 for |k - l| =
+// 0..3 (beta3'' is linear between integers, so these are exact). Lf[3k + j - 1] = L[k][k-j].
+static void spline_factor(int M, double theta, std::vector<double>& Lf, std::vector<double>& Dinv) {
+  auto A = [&](int k, int l) -> double {
+    const int d = k > l ? k - l : l - k;
+    if (d > 3) return 0.0;
+    if (theta == 0.0) return d == 0 ? 2.0 / 3.0 : (d == 1 ? 1.0 / 6.0 : 0.0);
+    double btb = 0.0;
+    if (d == 0) btb = (k == 0 || k == M - 1) ? (M == 1 ? 4.0 / 9.0 : 17.0 / 36.0) : 0.5;
+    else if (d == 1) btb = 2.0 / 9.0;
+    else if (d == 2) btb = 1.0 / 36.0;
+    const double g[4] = {8.0 / 3.0, -1.5, 0.0, 1.0 / 6.0};
+    return btb + theta * g[d];
+  };
+  Lf.assign((size_t)3 * M, 0.0);
+  Dinv.assign(M, 0.0);
+  std::vector<double> D(M, 0.0);
+  auto Lget = [&](int i, int k) { return (i > k && i - k <= 3) ? Lf[3 * i + (i - k) - 1] : (i == k ? 1.0 : 0.0); };
+  for (int k = 0; k < M; ++k) {
+    double d = A(k, k);
+    for (int j = 1; j <= 3 && k - j >= 0; ++j) d -= Lget(k, k - j) * Lget(k, k - j) * D[k - j];
+    D[k] = d;
+    Dinv[k] = 1.0 / d;
+    for (int i = k + 1; i <= k + 3 && i < M; ++i) {
+      double v = A(i, k);
+      for (int m = 1; m <= 3 && k - m >= 0; ++m) v -= Lget(i, k - m) * Lget(k, k - m) * D[k - m];
+      Lf[3 * i + (i - k) - 1] = v / d;
+    }
+  }
 }
 
 LineArgs epi::make_line_args(const epi_grid* grid, const float* Ip, const float* Im) {
@@ -395,6 +435,7 @@ LineArgs epi::make_line_args(const epi_grid* grid, const float* Ip, const float*
   a.beta = (float)grid->beta;
   a.gamma = (float)grid->gamma;
   a.nblk = line_blocks(a);
+  a.model = grid->image_model;
   return a;
 }
 
@@ -473,8 +514,37 @@ static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float*
   CHKLAUNCH();
   HIPCHK(hipMemcpyAsync(p->st_h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
   HIPCHK(hipStreamSynchronize(p->exec));
+  if (p->st_h->gTd != 0.0) {
+    leave(p);
+    return fail(EPI_ENUMERIC, "images contain %.0f non-finite values", p->st_h->gTd);
+  }
+  if (grid->image_model == EPI_IMAGE_SPLINE) {
+    // the kernels read the spline coefficients of both images where the linear model reads
+    // the samples
+    std::vector<double> Lf, Dinv;
+    spline_factor(M, grid->theta, Lf, Dinv);
+    double *dL = nullptr, *dD = nullptr, *Y = nullptr;
+    const size_t nbc = (size_t)p->N * sizeof(float);
+    HIPCHK(hipMalloc(&p->wp, nbc));
+    HIPCHK(hipMalloc(&p->wm, nbc));
+    HIPCHK(hipMalloc(&dL, Lf.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&dD, Dinv.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&Y, (size_t)p->N * sizeof(double)));
+    HIPCHK(hipMemcpy(dL, Lf.data(), Lf.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dD, Dinv.data(), Dinv.size() * sizeof(double), hipMemcpyHostToDevice));
+    const int normal = grid->theta > 0.0 ? 1 : 0;
+    launch_spline_coef(p->exec, Ip, p->wp, Y, M, p->L, normal, dL, dD);
+    launch_spline_coef(p->exec, Im, p->wm, Y, M, p->L, normal, dL, dD);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(p->exec);
+    (void)hipFree(dL);
+    (void)hipFree(dD);
+    (void)hipFree(Y);
+    if (e != hipSuccess) return fail(EPI_EHIP, "spline coefficients: %s", hipGetErrorString(e));
+    p->la.Ip = p->wp;
+    p->la.Im = p->wm;
+  }
   leave(p);
-  if (p->st_h->gTd != 0.0) return fail(EPI_ENUMERIC, "images contain %.0f non-finite values", p->st_h->gTd);
   return EPI_OK;
 }
 

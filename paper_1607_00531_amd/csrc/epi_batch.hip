@@ -482,6 +482,8 @@ EPI_API epi_status epi_batch_admit(epi_batch* bt, const epi_grid* grid, const fl
     epi_status vo = validate_rho_opts(opts);
     if (vo != EPI_OK) return vo;
   }
+  if (grid->image_model != EPI_IMAGE_LINEAR)
+    return fail(EPI_ENOTSUP, "the batched engine takes the linear image model only");
   const int64_t fp = epi_batch_footprint(grid, opts->max_iter);
   int sid = -1;
   for (int i = 0; i < bt->max_slots; ++i)

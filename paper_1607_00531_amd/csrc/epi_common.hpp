@@ -19,6 +19,8 @@ struct LineArgs {
   float v;           // cell volume
   float alpha, beta, gamma;
   int nblk;          // workgroups of the launch (for the XCD remap)
+  int model;         // image model: 0 linear (Ip, Im are the samples), 1 cubic B-spline
+                     // (Ip, Im are the spline coefficients of the two images)
 };
 
 // Device-resident scalars of the iterative solvers. Written by the single-block

@@ -60,6 +60,10 @@ void launch_matvec(hipStream_t s, int P, LineArgs a, const float* z, const float
                    float* pnew, const float* hdiag, const float* hoff, float* q, double* partial,
                    const DevState* st);
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial);
+// cubic B-spline coefficients of the N = M L samples T into W (one lane per line; Y: N
+// doubles of scratch; Lf, Dinv: the host factorisation of the line system)
+void launch_spline_coef(hipStream_t s, const float* T, float* W, double* Y, int M, int L,
+                        int normal, const double* Lf, const double* Dinv);
 // partial sums of u'(b - z) (the multiplier term of the augmented Lagrangian)
 void launch_udot(hipStream_t s, long long n, const float* u, const float* b, const float* z,
                  double* partial);

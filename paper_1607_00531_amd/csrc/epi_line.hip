@@ -17,7 +17,7 @@ namespace epi {
 // of H_D + alpha v D1'D1 + Hess P + gamma I. If d != null the field is b + lam d with
 // lam = 2^-trial (line search trial; skipped once the line search has accepted).
 // ------------------------------------------------------------------------------------
-template <int P, int MODE>
+template <int P, int MODE, int MODEL>
 __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restrict__ bsrc,
                                                const float* __restrict__ dsrc, int trial,
                                                int with_pen, float* __restrict__ grad,
@@ -27,7 +27,8 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
   if (dsrc != nullptr && st->ls_done) return;
   // per wave: the two image lines, its own field line (read by the neighbouring waves too),
   // the k - 1 and k + 1 lines and, for the workgroup's end waves, the outer j neighbour
-  __shared__ float sbuf[EPI_LINE_WAVES][6][LineBuf<P>::SIZE];
+  __shared__ float sraw[EPI_LINE_WAVES][LinePad + 6 * LineBuf<P>::SIZE];
+  const auto sbuf = [&](int w, int q) { return &sraw[w][LinePad + q * LineBuf<P>::SIZE]; };
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int blk = xcd_remap(blockIdx.x, a.nblk);
   const int line = blk * EPI_LINE_WAVES + wave;
@@ -40,8 +41,8 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
   const bool jm_lds = j0 && wave > 0, jp_lds = j1 && wave < EPI_LINE_WAVES - 1;
   const int jo = (wave == 0) ? lc - 1 : lc + 1;
   const bool jo_need = (wave == 0) ? j0 : (wave == EPI_LINE_WAVES - 1 ? j1 : false);
-  float* sIp = sbuf[wave][0];
-  float* sIm = sbuf[wave][1];
+  float* sIp = sbuf(wave, 0);
+  float* sIm = sbuf(wave, 1);
   float b[P], nb[4][P];   // nb: j - 1, j + 1, k - 1, k + 1 (a missing neighbour: b itself)
   {
     // every global load of the wavefront in one round trip (a second one for d)
@@ -68,14 +69,18 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
 #pragma unroll
     for (int q = 0; q < 6; ++q)
 #pragma unroll
-      for (int j = 0; j < P; ++j) sbuf[wave][q][lds_pad(lane + 64 * j)] = v[q][j];
+      for (int j = 0; j < P; ++j) sbuf(wave, q)[lds_pad(lane + 64 * j)] = v[q][j];
+    if (MODEL == 1) {
+      pad_spline_line(sIp, a.M, lane);
+      pad_spline_line(sIm, a.M, lane);
+    }
     __syncthreads();
-    const float* own = sbuf[wave][2];
-    const float* jm = jm_lds ? sbuf[wave - 1][2] : (wave == 0 && j0 ? sbuf[wave][5] : own);
-    const float* jp = jp_lds ? sbuf[wave + 1][2]
-                             : (wave == EPI_LINE_WAVES - 1 && j1 ? sbuf[wave][5] : own);
-    const float* km = k0 ? sbuf[wave][3] : own;
-    const float* kp = k1 ? sbuf[wave][4] : own;
+    const float* own = sbuf(wave, 2);
+    const float* jm = jm_lds ? sbuf(wave - 1, 2) : (wave == 0 && j0 ? sbuf(wave, 5) : own);
+    const float* jp = jp_lds ? sbuf(wave + 1, 2)
+                             : (wave == EPI_LINE_WAVES - 1 && j1 ? sbuf(wave, 5) : own);
+    const float* km = k0 ? sbuf(wave, 3) : own;
+    const float* kp = k1 ? sbuf(wave, 4) : own;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       const int t = lds_pad(P * lane + j);
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
   }
 
   Cells<P> C;
-  eval_cells<P>(a, b, sIp, sIm, lane, C);
+  eval_cells<P, false, MODEL>(a, b, sIp, sIm, lane, C);
 
   double acc[NQ_EVAL] = {0, 0, 0, 0, 0, 0};
   float phid[P], phidd[P];
@@ -166,9 +171,9 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
         out[2][j] = ofv;
       }
       float* dst[3] = {grad + (size_t)lc * NF, hdiag + (size_t)lc * NF, hoff + (size_t)lc * NF};
-      stage_out_n<P, 3>(dst, NF, valid, sbuf[wave][3], out, lane);
+      stage_out_n<P, 3>(dst, NF, valid, sbuf(wave, 3), out, lane);
     } else if (grad != nullptr) {
-      stage_out<P>(grad + (size_t)lc * NF, NF, valid, sbuf[wave][3], out[0], lane);
+      stage_out<P>(grad + (size_t)lc * NF, NF, valid, sbuf(wave, 3), out[0], lane);
     }
   }
   block_partials<NQ_EVAL>(acc, partial, blockIdx.x);
@@ -412,7 +417,7 @@ __global__ __launch_bounds__(256) void k_sgs_level(LineArgs a, int level, int km
   stage_out<P>(z + base, NF, valid, &sbuf[wave][0][0], x, lane);
 }
 
-template <int P>
+template <int P, int MODEL>
 __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restrict__ bvec,
                                                     const float* __restrict__ zvec,
                                                     const float* __restrict__ uvec,
@@ -423,7 +428,7 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int line = blockIdx.x * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
-  const bool hard = bstep_line_body<P>(a, (float)st->rho, (float)st->u_scale, bvec, zvec, uvec, wvec,
+  const bool hard = bstep_line_body<P, MODEL>(a, (float)st->rho, (float)st->u_scale, bvec, zvec, uvec, wvec,
                                        valid ? line : 0, valid, &sbuf[wave][LinePad], lane,
                                        &st->numeric_bad);
   if (valid && hard && lane == 0) {
@@ -435,11 +440,12 @@ __global__ __launch_bounds__(256) void k_admm_bstep(LineArgs a, float* __restric
 // Distortion-corrected images (Section 2, the model relation behind eq. D):
 // I+(x + A b)(1 + D1 b) and I-(x - A b)(1 - D1 b) at the cell centres of each line, and
 // float64 sums of the pair for the SSD and NCC quality measures. outp / outm may be null.
-template <int P>
+template <int P, int MODEL>
 __global__ __launch_bounds__(256) void k_correct(LineArgs a, const float* __restrict__ bsrc,
                                                  float* __restrict__ outp,
                                                  float* __restrict__ outm, double* partial) {
-  __shared__ float sbuf[EPI_LINE_WAVES][4][LineBuf<P>::SIZE];
+  __shared__ float sraw[EPI_LINE_WAVES][LinePad + 4 * LineBuf<P>::SIZE];
+  float* sw = &sraw[threadIdx.x >> 6][LinePad];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int line = xcd_remap(blockIdx.x, a.nblk) * EPI_LINE_WAVES + wave;
   const bool valid = line < a.L;
@@ -449,9 +455,13 @@ __global__ __launch_bounds__(256) void k_correct(LineArgs a, const float* __rest
                           bsrc + (size_t)lc * NF};
   const int cnt[3] = {a.M, a.M, NF};
   float v[3][P];
-  stage_in_n<P, 3>(srcs, cnt, valid, &sbuf[wave][0][0], v, lane);
-  const float* sIp = sbuf[wave][0];
-  const float* sIm = sbuf[wave][1];
+  stage_in_n<P, 3>(srcs, cnt, valid, sw, v, lane);
+  float* sIp = sw;
+  float* sIm = sw + LineBuf<P>::SIZE;
+  if (MODEL == 1) {
+    pad_spline_line(sIp, a.M, lane);
+    pad_spline_line(sIm, a.M, lane);
+  }
   const float bnext = shfl_down0(v[2][0], 1, lane);
   float ov[2][P];
   double acc[NQ_QUALITY] = {0, 0, 0, 0, 0, 0};
@@ -462,8 +472,13 @@ __global__ __launch_bounds__(256) void k_correct(LineArgs a, const float* __rest
     const float aidx = 0.5f * (bl + br) * a.inv_hp;
     const float g = (br - bl) * a.inv_hp;
     float ipv, ipd, imv, imd;
-    interp_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
-    interp_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
+    if (MODEL == 1) {
+      interp_spline_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
+      interp_spline_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
+    } else {
+      interp_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
+      interp_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
+    }
     const bool in = valid && c < a.M;
     const float cp = in ? ipv * (1.0f + g) : 0.0f;
     const float cm = in ? imv * (1.0f - g) : 0.0f;
@@ -480,12 +495,12 @@ __global__ __launch_bounds__(256) void k_correct(LineArgs a, const float* __rest
   const bool store = valid && outp != nullptr && outm != nullptr;
   float* outs[2] = {store ? outp + (size_t)lc * a.M : nullptr,
                     store ? outm + (size_t)lc * a.M : nullptr};
-  stage_out_n<P, 2>(outs, a.M, store, &sbuf[wave][2][0], ov, lane);
+  stage_out_n<P, 2>(outs, a.M, store, sw + 2 * LineBuf<P>::SIZE, ov, lane);
   block_partials<NQ_QUALITY>(acc, partial, blockIdx.x);
 }
 
 // Hard lines of the b-step: one wavefront per line (see hard_line_body).
-template <int P>
+template <int P, int MODEL>
 __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __restrict__ bvec,
                                                         const float* __restrict__ zvec,
                                                         const float* __restrict__ uvec,
@@ -496,7 +511,7 @@ __global__ __launch_bounds__(64) void k_admm_bstep_hard(LineArgs a, float* __res
   if ((int)blockIdx.x >= nhard) return;
   __shared__ HardLds<P> L;
   for (int h = blockIdx.x; h < nhard; h += gridDim.x)
-    hard_line_body<P>(a, (float)st->rho, (float)st->u_scale, bvec, zvec, uvec, wvec, hard_list[h], L, threadIdx.x,
+    hard_line_body<P, MODEL>(a, (float)st->rho, (float)st->u_scale, bvec, zvec, uvec, wvec, hard_list[h], L, threadIdx.x,
                       &st->max_active, st->qp_max_iter);
 }
 
@@ -510,16 +525,27 @@ void launch_eval(hipStream_t s, int P, int mode, LineArgs a, const float* b, con
                  double* partial, const DevState* st) {
   const int nb = line_blocks(a);
   a.nblk = nb;
-  if (mode == 0) {
-    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_eval<PP, 0>), dim3(nb), dim3(256), 0, s, a, b, d,
-                                         trial, with_pen, grad, hdiag, hoff, partial, st));
-  } else if (mode == 1) {
-    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_eval<PP, 1>), dim3(nb), dim3(256), 0, s, a, b, d,
-                                         trial, with_pen, grad, hdiag, hoff, partial, st));
+#define EPI_EVAL_LAUNCH(MD, ML)                                                              \
+  EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_eval<PP, MD, ML>), dim3(nb), dim3(256), 0, s, a, b, \
+                                       d, trial, with_pen, grad, hdiag, hoff, partial, st))
+  if (a.model == 1) {
+    if (mode == 0) {
+      EPI_EVAL_LAUNCH(0, 1);
+    } else if (mode == 1) {
+      EPI_EVAL_LAUNCH(1, 1);
+    } else {
+      EPI_EVAL_LAUNCH(2, 1);
+    }
   } else {
-    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_eval<PP, 2>), dim3(nb), dim3(256), 0, s, a, b, d,
-                                         trial, with_pen, grad, hdiag, hoff, partial, st));
+    if (mode == 0) {
+      EPI_EVAL_LAUNCH(0, 0);
+    } else if (mode == 1) {
+      EPI_EVAL_LAUNCH(1, 0);
+    } else {
+      EPI_EVAL_LAUNCH(2, 0);
+    }
   }
+#undef EPI_EVAL_LAUNCH
 }
 
 void launch_pcg_init(hipStream_t s, int P, LineArgs a, int precond, const float* grad,
@@ -541,8 +567,14 @@ void launch_pcg_update(hipStream_t s, int P, LineArgs a, int precond, const floa
 void launch_correct(hipStream_t s, int P, LineArgs a, const float* b, float* outp, float* outm,
                     double* partial) {
   const int nb = line_blocks(a);
-  EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_correct<PP>), dim3(nb), dim3(256), 0, s, a, b, outp,
-                                       outm, partial));
+  a.nblk = nb;
+  if (a.model == 1) {
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_correct<PP, 1>), dim3(nb), dim3(256), 0, s, a, b,
+                                         outp, outm, partial));
+  } else {
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_correct<PP, 0>), dim3(nb), dim3(256), 0, s, a, b,
+                                         outp, outm, partial));
+  }
 }
 
 void launch_precond(hipStream_t s, int P, LineArgs a, int precond, const float* hdiag,
@@ -575,13 +607,19 @@ void launch_sgs(hipStream_t s, int P, LineArgs a, const float* hdiag, const floa
 void launch_admm_bstep_part(hipStream_t s, int part, int P, LineArgs a, float* b,
                             const float* z, const float* u, float* w, int* hard_list,
                             DevState* st, int hard_blocks) {
-  if (part == 0) {
-    const int nb = line_blocks(a);
-    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep<PP>), dim3(nb), dim3(256), 0, s, a, b,
-                                         z, u, w, hard_list, st));
+  const int nb = line_blocks(a);
+  if (part == 0 && a.model == 1) {
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep<PP, 1>), dim3(nb), dim3(256), 0, s, a,
+                                         b, z, u, w, hard_list, st));
+  } else if (part == 0) {
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep<PP, 0>), dim3(nb), dim3(256), 0, s, a,
+                                         b, z, u, w, hard_list, st));
+  } else if (a.model == 1) {
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep_hard<PP, 1>), dim3(hard_blocks),
+                                         dim3(64), 0, s, a, b, z, u, w, hard_list, st));
   } else {
-    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep_hard<PP>), dim3(hard_blocks), dim3(64),
-                                         0, s, a, b, z, u, w, hard_list, st));
+    EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_admm_bstep_hard<PP, 0>), dim3(hard_blocks),
+                                         dim3(64), 0, s, a, b, z, u, w, hard_list, st));
   }
 }
 

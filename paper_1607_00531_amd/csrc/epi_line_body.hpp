@@ -48,8 +48,56 @@ __device__ __forceinline__ void interp_lds_z(const float* sT, int M, int c, floa
   der = (t1 - t0) * inv_hp;
 }
 
-// Floats reserved in front of a zero-padded line buffer (lds_pad(-2) = -3).
+// The cubic B-spline image model (the smoothed spline of the Section 5 comparison): value
+// and physical derivative of I(s) = sum_k w_k beta3(s - k) at s = c + disp from the
+// coefficients w of one line held in LDS, which must carry zero coefficients at the
+// indices -3, -2, -1 and M, M + 1, M + 2 (pad_spline_line). The segment k = floor(disp) + c
+// is clamped into [-2, M], so the four taps k - 1 .. k + 2 stay inside the padded buffer;
+// outside the support (k < -2 or k > M) the result is zero. The floor is taken of the
+// displacement alone, as in interp_lds.
+__device__ __forceinline__ void interp_spline_lds(const float* sW, int M, int c, float disp,
+                                                  float inv_hp, float& val, float& der) {
+  disp = fminf(fmaxf(disp, -(float)(2 * M + 8)), (float)(2 * M + 8));
+  const float fl = floorf(disp);
+  const int k = c + (int)fl;
+  const int kc = min(max(k, -2), M);
+  const float f = disp - fl;
+  const float g = 1.0f - f;
+  const float f2 = f * f, f3 = f2 * f;
+  const float w0 = g * g * g * (1.0f / 6.0f);
+  const float w1 = 0.5f * f3 - f2 + (2.0f / 3.0f);
+  const float w2 = -0.5f * f3 + 0.5f * f2 + 0.5f * f + (1.0f / 6.0f);
+  const float w3 = f3 * (1.0f / 6.0f);
+  const float d0 = -0.5f * g * g;
+  const float d1 = 1.5f * f2 - 2.0f * f;
+  const float d2 = -1.5f * f2 + f + 0.5f;
+  const float d3 = 0.5f * f2;
+  const float c0 = sW[lds_pad(kc - 1)], c1 = sW[lds_pad(kc)], c2 = sW[lds_pad(kc + 1)],
+              c3 = sW[lds_pad(kc + 2)];
+  const bool in = k == kc;
+  const float v = fmaf(w0, c0, fmaf(w1, c1, fmaf(w2, c2, w3 * c3)));
+  const float d = fmaf(d0, c0, fmaf(d1, c1, fmaf(d2, c2, d3 * c3)));
+  val = in ? v : 0.0f;
+  der = in ? d * inv_hp : 0.0f;
+}
+
+// Floats reserved in front of a zero-padded line buffer (lds_pad(-3) = -4).
 constexpr int LinePad = 4;
+
+// Zero coefficients around one staged spline line: indices -3, -2, -1 (the LinePad floats
+// in front of the buffer; for a second buffer they fall on the first one's zero tail) and
+// M, M + 1, M + 2 (inside the buffer). One lane writes them; the wavefront's LDS accesses
+// are performed in order.
+__device__ __forceinline__ void pad_spline_line(float* sW, int M, int lane) {
+  if (lane == 0) {
+    sW[lds_pad(-3)] = 0.0f;
+    sW[lds_pad(-2)] = 0.0f;
+    sW[lds_pad(-1)] = 0.0f;
+    sW[lds_pad(M)] = 0.0f;
+    sW[lds_pad(M + 1)] = 0.0f;
+    sW[lds_pad(M + 2)] = 0.0f;
+  }
+}
 
 // Writes the zero padding of interp_lds_z for one staged line (one lane of the wavefront
 // that reads it; LDS accesses of a wavefront are performed in order, so its other lanes see
@@ -70,7 +118,7 @@ struct Cells {
   float g[P], r[P], Jl[P], Jr[P];
 };
 
-template <int P, bool PADDED = false>
+template <int P, bool PADDED = false, int MODEL = 0>
 __device__ __forceinline__ void eval_cells(const LineArgs& a, const float (&b)[P],
                                            const float* sIp, const float* sIm, int lane,
                                            Cells<P>& C) {
@@ -83,7 +131,10 @@ __device__ __forceinline__ void eval_cells(const LineArgs& a, const float (&b)[P
     const float aidx = 0.5f * (b[j] + bR) * a.inv_hp;
     const float g = (bR - b[j]) * a.inv_hp;
     float ipv, ipd, imv, imd;
-    if (PADDED) {
+    if (MODEL == 1) {
+      interp_spline_lds(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
+      interp_spline_lds(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
+    } else if (PADDED) {
       interp_lds_z(sIp, a.M, c, aidx, a.inv_hp, ipv, ipd);
       interp_lds_z(sIm, a.M, c, -aidx, a.inv_hp, imv, imd);
     } else {
@@ -124,13 +175,13 @@ __device__ __forceinline__ float cross_diag(const LineArgs& a, int jj, int kk) {
 //   G = H_D(b^k) + alpha v D1'D1 + rho v I          (SPD tridiagonal)
 // and the QP  min 1/2 x'Gx + c'x  s.t.  -1 <= D1 (b^k + x) <= 1.
 // ------------------------------------------------------------------------------------
-template <int P, bool PADDED = false>
+template <int P, bool PADDED = false, int MODEL = 0>
 __device__ __forceinline__ void qp_data(const LineArgs& a, float rho, const float (&b)[P],
                                         const float (&z)[P], const float (&u)[P],
                                         const float* sIp, const float* sIm, int lane,
                                         float (&Gd)[P], float (&Go)[P], float (&c)[P],
                                         float (&g)[P], Cells<P>& C) {
-  eval_cells<P, PADDED>(a, b, sIp, sIm, lane, C);
+  eval_cells<P, PADDED, MODEL>(a, b, sIp, sIm, lane, C);
   float Jrr[P], rpJ[P], gprev[P], JrPrev[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) Jrr[j] = C.Jr[j] * C.r[j];
@@ -246,7 +297,7 @@ __device__ __forceinline__ void qp_solve_refined(const LineArgs& a, float rho, c
 // place) and w = b^{k+1} + u^k. sw: this wave's five LDS line buffers, preceded by LinePad
 // floats that receive the zero padding of the first image line. Every wave of the
 // workgroup must call it (barriers).
-template <int P>
+template <int P, int MODEL = 0>
 __device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho, float us,
                                                 float* __restrict__ bvec,
                                                 const float* __restrict__ zvec,
@@ -262,8 +313,13 @@ __device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho, fl
   float* sIp = sw;
   float* sIm = sw + LineBuf<P>::SIZE;
   stage_in_n<P, 5>(srcs, cnt, valid, sw, v, lane);
-  zero_pad_line(sIp, a.M, lane);
-  zero_pad_line(sIm, a.M, lane);
+  if (MODEL == 1) {
+    pad_spline_line(sIp, a.M, lane);
+    pad_spline_line(sIm, a.M, lane);
+  } else {
+    zero_pad_line(sIp, a.M, lane);
+    zero_pad_line(sIm, a.M, lane);
+  }
   float b[P], z[P], u[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -273,7 +329,7 @@ __device__ __forceinline__ bool bstep_line_body(const LineArgs& a, float rho, fl
   }
   float Gd[P], Go[P], c[P], g[P];
   Cells<P> C;
-  qp_data<P, true>(a, rho, b, z, u, sIp, sIm, lane, Gd, Go, c, g, C);
+  qp_data<P, true, MODEL>(a, rho, b, z, u, sIp, sIm, lane, Gd, Go, c, g, C);
   float x[P], mc[P];
   bool hard = false;
 #pragma unroll
@@ -438,7 +494,8 @@ __device__ inline int active_set_serial(int N, float hp, const float* Gd, const 
 // lane 0 (active_set_serial), then b^{k+1} and w written back. One wavefront per workgroup.
 template <int P>
 struct HardLds {
-  float sIp[LineBuf<P>::SIZE], sIm[LineBuf<P>::SIZE], stg[LineBuf<P>::SIZE];
+  float simg[LinePad + 2 * LineBuf<P>::SIZE];   // the two image lines after LinePad floats
+  float stg[LineBuf<P>::SIZE];
   float Gd[64 * P], Go[64 * P], cv[64 * P], g0[64 * P], x[64 * P], p[64 * P], o[64 * P],
       q[64 * P], rd[64 * P], ro[64 * P], rr[64 * P];
   int grp[64 * P];
@@ -446,7 +503,7 @@ struct HardLds {
   int res;
 };
 
-template <int P>
+template <int P, int MODEL = 0>
 __device__ __forceinline__ void hard_line_body(const LineArgs& a, float rho, float us,
                                                float* __restrict__ bvec,
                                                const float* __restrict__ zvec,
@@ -456,9 +513,15 @@ __device__ __forceinline__ void hard_line_body(const LineArgs& a, float rho, flo
                                                int qp_max) {
   const int NF = a.M + 1;
   const size_t base = (size_t)line * NF;
+  float* sIp = L.simg + LinePad;
+  float* sIm = sIp + LineBuf<P>::SIZE;
   for (int t = lane; t < 64 * P; t += 64) {
-    L.sIp[lds_pad(t)] = (t < a.M) ? a.Ip[(size_t)line * a.M + t] : 0.0f;
-    L.sIm[lds_pad(t)] = (t < a.M) ? a.Im[(size_t)line * a.M + t] : 0.0f;
+    sIp[lds_pad(t)] = (t < a.M) ? a.Ip[(size_t)line * a.M + t] : 0.0f;
+    sIm[lds_pad(t)] = (t < a.M) ? a.Im[(size_t)line * a.M + t] : 0.0f;
+  }
+  if (MODEL == 1) {
+    pad_spline_line(sIp, a.M, lane);
+    pad_spline_line(sIm, a.M, lane);
   }
   float b[P], z[P], u[P];
   stage_in<P>(bvec + base, NF, true, L.stg, b, lane);
@@ -468,7 +531,7 @@ __device__ __forceinline__ void hard_line_body(const LineArgs& a, float rho, flo
   for (int j = 0; j < P; ++j) u[j] *= us;
   float Gdr[P], Gor[P], cr[P], gr[P];
   Cells<P> C;
-  qp_data<P>(a, rho, b, z, u, L.sIp, L.sIm, lane, Gdr, Gor, cr, gr, C);
+  qp_data<P, false, MODEL>(a, rho, b, z, u, sIp, sIm, lane, Gdr, Gor, cr, gr, C);
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int i = P * lane + j;

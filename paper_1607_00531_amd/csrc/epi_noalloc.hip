@@ -57,6 +57,8 @@ EPI_API epi_status epi_objective_noalloc(const epi_grid* grid, const float* d_Ip
   if (!grid || !d_Iplus || !d_Iminus || !d_b || !d_terms) return fail(EPI_EINVAL, "null argument");
   epi_status vs = validate_grid(grid);
   if (vs != EPI_OK) return vs;
+  if (grid->image_model != EPI_IMAGE_LINEAR)
+    return fail(EPI_ENOTSUP, "the spline image model needs its coefficients from epi_setup");
   const LineArgs a = make_line_args(grid, d_Iplus, d_Iminus);
   const int lb = line_blocks(a);
   const size_t need = (size_t)lb * NQ_EVAL * sizeof(double);

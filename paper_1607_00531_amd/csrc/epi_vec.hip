@@ -149,6 +149,48 @@ __global__ __launch_bounds__(256) void k_udot(long long n, const float* __restri
   block_partials<1>(acc, partial, blockIdx.x);
 }
 
+// Coefficients of the cubic B-spline image model: per PE line (one lane each, serial) the
+// banded SPD system A w = rhs with A = L D L' factored once on the host in float64 (unit
+// lower L of half-width 3: Lf[3k + j - 1] = L[k][k - j]; Dinv[k] = 1 / D[k]). rhs = T (the
+// interpolating spline, A = B) or B T (the smoothed fit, A = B'B + theta G; B symmetric).
+// The forward sweep keeps y in the float64 scratch Y (N entries).
+__global__ __launch_bounds__(64) void k_spline_coef(const float* __restrict__ T,
+                                                    float* __restrict__ W, double* Y, int M,
+                                                    int L, int normal,
+                                                    const double* __restrict__ Lf,
+                                                    const double* __restrict__ Dinv) {
+  const int line = blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= L) return;
+  const float* t = T + (size_t)line * M;
+  double* y = Y + (size_t)line * M;
+  float* w = W + (size_t)line * M;
+  double y1 = 0.0, y2 = 0.0, y3 = 0.0;
+  for (int k = 0; k < M; ++k) {
+    double r = t[k];
+    if (normal) {
+      r *= 2.0 / 3.0;
+      if (k > 0) r += t[k - 1] * (1.0 / 6.0);
+      if (k < M - 1) r += t[k + 1] * (1.0 / 6.0);
+    }
+    const double yk = r - Lf[3 * k] * y1 - Lf[3 * k + 1] * y2 - Lf[3 * k + 2] * y3;
+    y[k] = yk;
+    y3 = y2;
+    y2 = y1;
+    y1 = yk;
+  }
+  double x1 = 0.0, x2 = 0.0, x3 = 0.0;
+  for (int k = M - 1; k >= 0; --k) {
+    const double a1 = k + 1 < M ? Lf[3 * (k + 1)] : 0.0;
+    const double a2 = k + 2 < M ? Lf[3 * (k + 2) + 1] : 0.0;
+    const double a3 = k + 3 < M ? Lf[3 * (k + 3) + 2] : 0.0;
+    const double xk = y[k] * Dinv[k] - a1 * x1 - a2 * x2 - a3 * x3;
+    w[k] = (float)xk;
+    x3 = x2;
+    x2 = x1;
+    x1 = xk;
+  }
+}
+
 // After a symmetric Gauss-Seidel application: the PCG partial sums with the new z, in the
 // order of the line kernel they replace (first = 1: r.z, r.r as at the PCG start, and
 // p = z; first = 0: r.r, r.z as in the update). gate: skip once the PCG has stopped.
@@ -385,6 +427,11 @@ void launch_matvec(hipStream_t s, int P, LineArgs a, const float* z, const float
 }
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial) {
   hipLaunchKernelGGL(k_dot, dim3(flat_blocks(n)), dim3(256), 0, s, n, x, y, partial);
+}
+void launch_spline_coef(hipStream_t s, const float* T, float* W, double* Y, int M, int L,
+                        int normal, const double* Lf, const double* Dinv) {
+  hipLaunchKernelGGL(k_spline_coef, dim3((L + 63) / 64), dim3(64), 0, s, T, W, Y, M, L, normal,
+                     Lf, Dinv);
 }
 void launch_udot(hipStream_t s, long long n, const float* u, const float* b, const float* z,
                  double* partial) {

@@ -30,7 +30,10 @@ class EpiError(RuntimeError):
 class Grid(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("m", C.c_int32 * 3), ("h", C.c_double * 3),
                 ("alpha", C.c_double), ("beta", C.c_double), ("gamma", C.c_double),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("image_model", C.c_int32), ("theta", C.c_double)]
+
+
+IMAGE_MODELS = {"linear": 0, "spline": 1}
 
 
 class Terms(C.Structure):
@@ -54,7 +57,7 @@ class GNReport(C.Structure):
 
 # penalty strategies of epi_admm_opts.rho_mode
 RHO_MODES = {"fixed": 0, "adapt": 1, "adapt_floor": 2}
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 
 class ADMMOpts(C.Structure):
@@ -193,7 +196,8 @@ class Problem:
     are kept referenced here for the lifetime of the handle."""
 
     def __init__(self, Ip, Im, h, alpha: float, beta: float = 10.0, gamma: float = 1e-3,
-                 precision: str = "mixed", ndim: Optional[int] = None, stream=None):
+                 precision: str = "mixed", ndim: Optional[int] = None, stream=None,
+                 image_model: str = "linear", theta: float = 0.0):
         if Ip.dim() != 3 or Ip.shape != Im.shape:
             raise ValueError("Ip and Im must have the same canonical shape (m3, m2, M)")
         m3, m2, M = (int(s) for s in Ip.shape)
@@ -212,6 +216,9 @@ class Problem:
             g.h[a] = self.h[a]
         g.alpha, g.beta, g.gamma = self.alpha, self.beta, self.gamma
         g.precision = PREC[precision]
+        self.image_model, self.theta = image_model, float(theta)
+        g.image_model = IMAGE_MODELS[image_model]
+        g.theta = self.theta
         self._h = C.c_void_p()
         _check(lib().epi_setup(C.byref(g), _ptr(Ip), _ptr(Im), _stream_handle(stream),
                                C.byref(self._h)))
@@ -393,11 +400,11 @@ def prolong_faces(coarse, fine, stream=None):
 
 def solve_multilevel_admm(Ip, Im, h, alpha, b, levels=3, beta=10.0, gamma=1e-3,
                           precision="mixed", ndim=None, stream=None, restart="average",
-                          **opts) -> dict:
+                          image_model="linear", theta=0.0, **opts) -> dict:
     """Coarse-to-fine ADMM (epi_solve_multilevel_admm); writes the finest field into b.
     restart: "prolong_all", "fine_b" or "average" (the three strategies of Section 4.4)."""
     L = _ml_sigs(lib())
-    g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, precision, ndim)
+    g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, precision, ndim, image_model, theta)
     o = ADMMOpts()
     L.epi_admm_default_opts(C.byref(o))
     for k, v in opts.items():
@@ -416,10 +423,11 @@ def solve_multilevel_admm(Ip, Im, h, alpha, b, levels=3, beta=10.0, gamma=1e-3,
 
 
 def solve_multilevel_gnpcg(Ip, Im, h, alpha, b, levels=3, beta=10.0, gamma=1e-3,
-                           precision="mixed", ndim=None, stream=None, **opts) -> dict:
+                           precision="mixed", ndim=None, stream=None, image_model="linear",
+                           theta=0.0, **opts) -> dict:
     """Coarse-to-fine GN-PCG (epi_solve_multilevel_gnpcg); writes the finest field into b."""
     L = _ml_sigs(lib())
-    g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, precision, ndim)
+    g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, precision, ndim, image_model, theta)
     o = GNOpts()
     L.epi_gn_default_opts(C.byref(o))
     for k, v in opts.items():
@@ -467,7 +475,8 @@ def _batch_sigs(L):
     return L
 
 
-def _grid_struct(shape_cells, h, alpha, beta, gamma, precision, ndim=None):
+def _grid_struct(shape_cells, h, alpha, beta, gamma, precision, ndim=None, image_model="linear",
+                 theta=0.0):
     m3, m2, M = (int(s) for s in shape_cells)
     g = Grid()
     g.ndim = ndim if ndim is not None else (2 if m3 == 1 else 3)
@@ -476,6 +485,8 @@ def _grid_struct(shape_cells, h, alpha, beta, gamma, precision, ndim=None):
         g.h[a] = float(h[a])
     g.alpha, g.beta, g.gamma = float(alpha), float(beta), float(gamma)
     g.precision = PREC[precision]
+    g.image_model = IMAGE_MODELS[image_model]
+    g.theta = float(theta)
     return g
 
 
@@ -499,10 +510,13 @@ class Batch:
         g = _grid_struct(shape_cells, h, alpha, 10.0, 1e-3, "mixed")
         return int(_batch_sigs(lib()).epi_batch_footprint(C.byref(g), int(max_iter)))
 
-    def admit(self, Ip, Im, h, alpha, b, z, u, beta=10.0, gamma=1e-3, ndim=None, **opts):
-        """Returns the slot index, or None when the engine is busy (EPI_EBUSY)."""
+    def admit(self, Ip, Im, h, alpha, b, z, u, beta=10.0, gamma=1e-3, ndim=None,
+              image_model="linear", theta=0.0, **opts):
+        """Returns the slot index, or None when the engine is busy (EPI_EBUSY). The engine
+        takes the linear image model only (EPI_ENOTSUP otherwise)."""
         L = _batch_sigs(lib())
-        g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, self.precision, ndim)
+        g = _grid_struct(tuple(Ip.shape), h, alpha, beta, gamma, self.precision, ndim,
+                         image_model, theta)
         o = ADMMOpts()
         L.epi_admm_default_opts(C.byref(o))
         for k, v in opts.items():

@@ -95,3 +95,26 @@ def gn_history_compare(rep, ro, rtol):
         return k - 1
     np.testing.assert_allclose(rep["J"], ro.J, rtol=rtol)
     return k
+
+
+def gn_step_tol(P, b, precond="block", eta=0.1, maxit=30, seeds=(1, 2)):
+    """Bar for J after one GN-PCG step from b against the oracle's: J_REL |J(b)| plus 16
+    times the change of J(b + d) when every Hessian block entry and every gradient entry
+    takes one random relative perturbation of 2^-24 (one float32 rounding) before the PCG
+    solve, the largest over `seeds`. The GPU assembles both in float32; on PE lines of a
+    few hundred faces the block-Jacobi systems amplify those roundings to ~1e-4 voxels in
+    the direction, and J after a step that removes most of the misfit inherits that."""
+    import oracle as O
+    bl = P.lines(b)
+    g = O.gradient(P, bl, True)
+    tri = O.hessian_tridiag(P, bl, True)
+    d, _, _ = O.pcg(P, tri, -g, precond, eta, maxit)
+    J1 = O.objective(P, bl + d, True)["J"]
+    sens = 0.0
+    for seed in seeds:
+        rng = np.random.default_rng(seed)
+        trp = tuple(t * (1.0 + 2.0 ** -24 * rng.uniform(-1.0, 1.0, size=t.shape)) for t in tri)
+        gp = g * (1.0 + 2.0 ** -24 * rng.uniform(-1.0, 1.0, size=g.shape))
+        dp, _, _ = O.pcg(P, trp, -gp, precond, eta, maxit)
+        sens = max(sens, abs(O.objective(P, bl + dp, True)["J"] - J1))
+    return J_REL * abs(O.objective(P, bl, True)["J"]) + 16.0 * sens
