@@ -526,6 +526,49 @@ def precond_leg(dev, gn_steps=3, applies=5):
     return out
 
 
+def spline_leg(imgs, vols, steps, isolated_reps, thetas=(0.0, 0.5)):
+    """The smoothed cubic-spline image model (Section 5's comparison model) on the headline
+    volumes, beside the linear model: set-up time of a problem (which computes both images'
+    coefficients), ADMM solves to the same tolerance, and the b-step kernel launched back to
+    back. The b-step moves the same bytes under both models (the coefficients replace the
+    samples), so its time ratio is the cost of the four-tap evaluation."""
+    import torch
+    from paper_1607_00531_amd import Problem
+    m3, m2, M = imgs[0][0].shape
+    state = [torch.zeros((m3, m2, M + 1), device=imgs[0][0].device) for _ in range(3)]
+    out = {"workload": f"ADMM to rel. residual {TOL:g}, the first {steps} headline volumes, "
+                       f"mixed precision; theta in grid units"}
+    for model, theta in [("linear", 0.0)] + [("spline", t) for t in thetas]:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        probs = [Problem(Ip, Im, v.h, ALPHA, BETA, precision="mixed", image_model=model,
+                         theta=theta) for (Ip, Im), v in list(zip(imgs, vols))[:steps]]
+        torch.cuda.synchronize()
+        setup = (time.perf_counter() - t0) / len(probs)
+        iters = []
+        t0 = time.perf_counter()
+        for pr in probs:
+            for t in state:
+                t.zero_()
+            iters.append(pr.solve_admm(*state, rho=RHO, max_iter=MAX_ITER, eps_abs=0.0,
+                                       eps_rel=TOL, check_every=CHECK_EVERY)["iters"])
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        for t in state:
+            t.zero_()
+        prof = probs[0].solve_admm(*state, profile=True, isolated_reps=isolated_reps, rho=RHO,
+                                   max_iter=40, eps_abs=0.0, eps_rel=0.0)
+        key = model if model == "linear" else f"spline theta={theta:g}"
+        out[key] = {"setup_s_per_volume": round(setup, 4), "admm_iters": iters,
+                    "volumes_per_s": round(len(probs) / total, 3),
+                    "us_per_iteration": round(1e6 * total / max(sum(iters), 1), 2),
+                    "bstep_us_back_to_back": round(prof.get("kernel_us_isolated", {}).get("bstep", 0.0), 3)}
+        log(f"spline leg {key}: {json.dumps(out[key])}")
+        for pr in probs:
+            pr.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -545,6 +588,7 @@ def main():
     ap.add_argument("--batch-volumes", type=int, default=48)
     ap.add_argument("--batch-iters", type=int, default=40)
     ap.add_argument("--no-served", action="store_true", help="skip the request-stream leg")
+    ap.add_argument("--no-spline", action="store_true", help="skip the spline image model leg")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the preconditioner comparison on the 128x128x64 volume")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
@@ -710,6 +754,11 @@ def main():
         log("served leg")
         served = served_leg(dev, args.serve_seconds, args.serve_rate, args.serve_pool, MAX_ITER)
 
+    spline = None
+    if not args.no_spline:
+        log("spline image model leg")
+        spline = spline_leg(imgs, vols, min(4, len(vols)), args.isolated_reps)
+
     precond = None
     if not args.no_precond:
         log("preconditioner leg")
@@ -758,6 +807,7 @@ def main():
         "batched": batched,
         "served": served,
         "preconditioners": precond,
+        "spline_image_model": spline,
         "cpu_baseline": base,
         "error_vs_oracle": err,
     }
