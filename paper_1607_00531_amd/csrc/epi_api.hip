@@ -70,7 +70,7 @@ struct epi_problem {
   // workspace (n floats each)
   float *w = nullptr, *t1 = nullptr, *t2 = nullptr;
   float *g = nullptr, *hd = nullptr, *ho = nullptr, *x = nullptr, *r = nullptr, *zz = nullptr,
-        *p = nullptr, *q = nullptr;
+        *p = nullptr;
   double* partial = nullptr;     // general partial sums
   double* partial_e = nullptr;   // ADMM z/u epilogue
   size_t partial_cap = 0;
@@ -342,7 +342,7 @@ EPI_API void epi_destroy(epi_problem* p) {
   if (!p) return;
   if (p->exec) (void)hipStreamSynchronize(p->exec);
   free_graph(p);
-  void* bufs[] = {p->w, p->t1, p->t2, p->g, p->hd, p->ho, p->x, p->r, p->zz, p->p, p->q,
+  void* bufs[] = {p->w, p->t1, p->t2, p->g, p->hd, p->ho, p->x, p->r, p->zz, p->p,
                   p->partial, p->partial_e, p->st, p->hard_list, p->hist, p->wp, p->wm};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
@@ -480,7 +480,7 @@ static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float*
   const size_t zb = (grid->precision == EPI_PREC_MIXED && ce2 <= 128)
                         ? zop_bytes(p->m2, p->m3, 2 * ((ce2 + 15) / 16), (ce2 + 31) / 32)
                         : 0;
-  float** bufs[] = {&p->w, &p->t1, &p->t2, &p->g, &p->hd, &p->ho, &p->x, &p->r, &p->zz, &p->p, &p->q};
+  float** bufs[] = {&p->w, &p->t1, &p->t2, &p->g, &p->hd, &p->ho, &p->x, &p->r, &p->zz, &p->p};
   for (float** b : bufs) HIPCHK(hipMalloc(b, b == &p->t2 ? nb_al + zb : nb));
   if (zb) p->zop = reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(p->t2) + nb_al);
   const int lb = line_blocks(a);
@@ -1208,16 +1208,16 @@ EPI_API epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts
     for (int it = 0; it < opts->pcg_max; ++it) {
       float* pcur = pbuf[it & 1];
       if (it == 0)
-        launch_matvec(p->exec, p->P, p->la, nullptr, pcur, nullptr, p->hd, p->ho, p->q,
-                      p->partial, p->st);
+        launch_matvec(p->exec, p->P, p->la, nullptr, pcur, nullptr, p->hd, p->ho, p->partial,
+                      p->st);
       else
         launch_matvec(p->exec, p->P, p->la, p->zz, pbuf[(it - 1) & 1], pcur, p->hd, p->ho,
-                      p->q, p->partial, p->st);
+                      p->partial, p->st);
       f.kind = FIN_PCG_ALPHA;
       f.nb1 = lb;
       launch_finalize(p->exec, f, p->st);
       launch_pcg_update(p->exec, p->P, p->la, sgs ? EPI_PRECOND_NONE : opts->precond, p->hd,
-                        p->ho, p->x, p->r, p->zz, pcur, p->q, p->partial, p->st);
+                        p->ho, p->x, p->r, p->zz, pcur, p->partial, p->st);
       if (sgs) {
         launch_sgs(p->exec, p->P, p->la, p->hd, p->ho, p->r, p->zz, p->st, 1);
         launch_sgs_finish(p->exec, n, p->r, p->zz, nullptr, p->partial, 0, p->st);

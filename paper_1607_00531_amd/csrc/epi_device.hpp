@@ -200,6 +200,51 @@ __device__ __forceinline__ void store_stream(float* p, float v) {
 }
 
 // ------------------------------------------------------------------------------------
+// y = H_JGN p at the faces i = lane + 64 j of one PE line (lane-contiguous layout, eq.
+// dJGN): the line's tridiagonal block (diagonal hdv, off-diagonal hov, both along the
+// line) plus alpha v (D2'D2 + D3'D3) p, the Neumann Laplacian across lines, with the j -+ 1
+// neighbour lines from LDS (spm / spp, face order) or, where those are null, from pjo
+// (the outer j neighbour of a workgroup's end wavefront) and the k -+ 1 lines pk0 / pk1.
+// j0 / j1 / k0 / k1: the neighbour exists. The matvec and the PCG update both form q with
+// this one function, so the q the update subtracts is the q whose p.q the matvec summed.
+// ------------------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ void hjgn_apply(const LineArgs& a, int NF, int lane, bool j0, bool j1,
+                                           bool k0, bool k1, const float (&pc)[P],
+                                           const float (&hdv)[P], const float (&hov)[P],
+                                           const float (&pk0)[P], const float (&pk1)[P],
+                                           const float (&pjo)[P], const float* spm,
+                                           const float* spp, float (&y)[P]) {
+  const float av = a.alpha * a.v;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int i = lane + 64 * j;
+    // faces i - 1 and i + 1 (lane shifts; across a 64-face block from the end lane)
+    float pp = dpp_prev_lane(pc[j]), ho_p = dpp_prev_lane(hov[j]), pn = dpp_next_lane(pc[j]);
+    if (j > 0) {
+      const float e0 = read_lane(pc[j - 1], 63), e1 = read_lane(hov[j - 1], 63);
+      if (lane == 0) {
+        pp = e0;
+        ho_p = e1;
+      }
+    }
+    if (j < P - 1) {
+      const float e2 = read_lane(pc[j + 1], 0);
+      if (lane == 63) pn = e2;
+    }
+    float yy = hdv[j] * pc[j];
+    if (i > 0) yy = fmaf(ho_p, pp, yy);
+    if (i < NF - 1) yy = fmaf(hov[j], pn, yy);
+    float l2 = 0.0f, l3 = 0.0f;
+    if (j0) l2 += pc[j] - (spm ? spm[i] : pjo[j]);
+    if (j1) l2 += pc[j] - (spp ? spp[i] : pjo[j]);
+    if (k0) l3 += pc[j] - pk0[j];
+    if (k1) l3 += pc[j] - pk1[j];
+    y[j] = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, yy);
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // LDS staging of one PE line per wavefront (coalesced global access, blocked registers)
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ int lds_pad(int t) { return t + (t >> 5); }

@@ -33,9 +33,11 @@ void launch_eval(hipStream_t s, int P, int mode, LineArgs a, const float* b, con
 void launch_pcg_init(hipStream_t s, int P, LineArgs a, int precond, const float* grad,
                      const float* hdiag, const float* hoff, float* x, float* r, float* z,
                      float* p, double* partial);
+// x += alpha p, r -= alpha H_JGN p (q formed again from p and its neighbour lines),
+// z = Pinv r; partial sums r.r and r.z
 void launch_pcg_update(hipStream_t s, int P, LineArgs a, int precond, const float* hdiag,
                        const float* hoff, float* x, float* r, float* z, const float* p,
-                       const float* q, double* partial, const DevState* st);
+                       double* partial, const DevState* st);
 // z = Pinv r with a line-local preconditioner (BLOCK, JACOBI, NONE)
 void launch_precond(hipStream_t s, int P, LineArgs a, int precond, const float* hdiag,
                     const float* hoff, const float* r, float* z);
@@ -55,9 +57,10 @@ void launch_admm_bstep(hipStream_t s, int P, LineArgs a, float* b, const float* 
 int flat_blocks(long long n);
 void launch_correct(hipStream_t s, int P, LineArgs a, const float* b, float* outp, float* outm,
                     double* partial);
-// q = H_JGN p with p = pold (z null) or p = z + beta pold written to pnew (fused update)
+// partial sums p.q of q = H_JGN p with p = pold (z null) or p = z + beta pold written to
+// pnew (fused update); q itself is formed again by the PCG update
 void launch_matvec(hipStream_t s, int P, LineArgs a, const float* z, const float* pold,
-                   float* pnew, const float* hdiag, const float* hoff, float* q, double* partial,
+                   float* pnew, const float* hdiag, const float* hoff, double* partial,
                    const DevState* st);
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial);
 // cubic B-spline coefficients of the N = M L samples T into W (one lane per line; Y: N

@@ -251,48 +251,92 @@ __global__ __launch_bounds__(256) void k_pcg_init(LineArgs a, int precond,
   block_partials<NQ_PCG>(acc, partial, blockIdx.x);
 }
 
-// PCG update: x += alpha p, r -= alpha q, z = Pinv r; partial sums r.r and r.z.
+// PCG update: x += alpha p, r -= alpha q, z = Pinv r; partial sums r.r and r.z. q = H_JGN p
+// is formed here again from p (hjgn_apply, as in the matvec, with the same block -> line
+// map so that the j neighbours come from the same LDS exchange), instead of being stored by
+// the matvec and read back: the p lines of the k and outer j neighbours are L2 hits, so
+// the update reads x, r, p and the Hessian blocks from HBM and writes x, r and z.
 template <int P>
 __global__ __launch_bounds__(256) void k_pcg_update(LineArgs a, int precond,
-                                                    const float* __restrict__ hdiag,
-                                                    const float* __restrict__ hoff,
+                                                    const float* __restrict__ hd,
+                                                    const float* __restrict__ ho,
                                                     float* __restrict__ x, float* __restrict__ r,
                                                     float* __restrict__ z,
-                                                    const float* __restrict__ p,
-                                                    const float* __restrict__ q, double* partial,
+                                                    const float* __restrict__ p, double* partial,
                                                     const DevState* st) {
   if (st->pcg_done) return;
-  __shared__ float sbuf[EPI_LINE_WAVES][6][LineBuf<P>::SIZE];
+  __shared__ float sp[EPI_LINE_WAVES][64 * P];   // p of the workgroup's lines, face order
+  __shared__ float sbuf[EPI_LINE_WAVES][3][LineBuf<P>::SIZE];
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int line = blockIdx.x * EPI_LINE_WAVES + wave;
-  const bool valid = line < a.L;
-  const int lc = valid ? line : 0;
+  const int blk = xcd_remap(blockIdx.x, a.nblk);
+  const int line = blk * EPI_LINE_WAVES + wave;
+  const bool lv = line < a.L;
+  const int lc = lv ? line : 0;
   const int NF = a.M + 1;
+  const int jj = lc % a.m2, kk = lc / a.m2;
   const size_t base = (size_t)lc * NF;
   const float al = (float)st->alpha_cg;
-  // all six lines in one memory round trip: x, r, p, q, Hessian diagonal and off-diagonal
-  const float* srcs[6] = {x + base, r + base, p + base, q + base, hdiag + base, hoff + base};
-  const int cnt[6] = {NF, NF, NF, NF, NF, NF};
-  float v[6][P];
-  stage_in_n<P, 6>(srcs, cnt, valid, &sbuf[wave][0][0], v, lane);
-  float o[3][P];   // x, r, z
+  const bool j0 = jj > 0, j1 = jj < a.m2 - 1, k0 = kk > 0, k1 = kk < a.m3 - 1;
+  const bool jm_lds = j0 && wave > 0, jp_lds = j1 && wave < EPI_LINE_WAVES - 1;
+  const int jo = (wave == 0) ? lc - 1 : lc + 1;
+  const bool jo_need = (wave == 0) ? j0 : (wave == EPI_LINE_WAVES - 1 ? j1 : false);
+  const int lines[4] = {lc, k0 ? lc - a.m2 : lc, k1 ? lc + a.m2 : lc, jo_need ? jo : lc};
+  // every global load first: p of the four lines, x, r and the Hessian blocks of the own
+  float pv[4][P], xv[P], rv[P], hdv[P], hov[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    o[0][j] = fmaf(al, v[2][j], v[0][j]);
-    o[1][j] = fmaf(-al, v[3][j], v[1][j]);
-    o[2][j] = o[1][j];
+    const int i = lane + 64 * j;
+    const int ic = (j < P - 1 || i < NF) ? i : NF - 1;   // in bounds; replaced below
+#pragma unroll
+    for (int t = 0; t < 4; ++t) pv[t][j] = p[(size_t)lines[t] * NF + ic];
+    xv[j] = x[base + ic];
+    rv[j] = r[base + ic];
+    hdv[j] = hd[base + ic];
+    hov[j] = ho[base + ic];
   }
-  precond_apply<P>(a, precond, v[4], v[5], cross_diag(a, lc % a.m2, lc / a.m2), o[2], lane);
+  float pc[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int i = lane + 64 * j;
+    pc[j] = (lv && (j < P - 1 || i < NF)) ? pv[0][j] : 0.0f;
+    sp[wave][i] = pc[j];
+  }
+  __syncthreads();
+  float y[P];
+  hjgn_apply<P>(a, NF, lane, j0, j1, k0, k1, pc, hdv, hov, pv[1], pv[2], pv[3],
+                jm_lds ? sp[wave - 1] : nullptr, jp_lds ? sp[wave + 1] : nullptr, y);
+  // x and r in the lane-contiguous layout (coalesced stores); r and the Hessian blocks
+  // (zero past the line, as the preconditioner expects) to the lane-blocked layout
+  float t3[3][P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int i = lane + 64 * j;
+    const bool ok = lv && (j < P - 1 || i < NF);
+    const float xn = fmaf(al, pc[j], xv[j]);
+    const float rn = fmaf(-al, y[j], rv[j]);
+    if (ok) {
+      store_stream(&x[base + i], xn);
+      store_stream(&r[base + i], rn);
+    }
+    t3[0][j] = ok ? rn : 0.0f;
+    t3[1][j] = ok ? hdv[j] : 0.0f;
+    t3[2][j] = ok ? hov[j] : 0.0f;
+  }
+  float v[3][P];
+  regs_to_blocked_n<P, 3>(t3, &sbuf[wave][0][0], v, lane);
+  float zb[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) zb[j] = v[0][j];
+  precond_apply<P>(a, precond, v[1], v[2], cross_diag(a, jj, kk), zb, lane);
   double acc[NQ_PCG] = {0, 0};
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    if (valid && P * lane + j < NF) {
-      acc[0] += (double)o[1][j] * o[1][j];
-      acc[1] += (double)o[1][j] * o[2][j];
+    if (lv && P * lane + j < NF) {
+      acc[0] += (double)v[0][j] * v[0][j];
+      acc[1] += (double)v[0][j] * zb[j];
     }
   }
-  float* dst[3] = {x + base, r + base, z + base};
-  stage_out_n<P, 3>(dst, NF, valid, &sbuf[wave][0][0], o, lane);
+  stage_out<P>(z + base, NF, lv, &sbuf[wave][0][0], zb, lane);
   block_partials<NQ_PCG>(acc, partial, blockIdx.x);
 }
 
@@ -558,10 +602,11 @@ void launch_pcg_init(hipStream_t s, int P, LineArgs a, int precond, const float*
 
 void launch_pcg_update(hipStream_t s, int P, LineArgs a, int precond, const float* hdiag,
                        const float* hoff, float* x, float* r, float* z, const float* p,
-                       const float* q, double* partial, const DevState* st) {
+                       double* partial, const DevState* st) {
   const int nb = line_blocks(a);
+  a.nblk = nb;
   EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_pcg_update<PP>), dim3(nb), dim3(256), 0, s, a,
-                                       precond, hdiag, hoff, x, r, z, p, q, partial, st));
+                                       precond, hdiag, hoff, x, r, z, p, partial, st));
 }
 
 void launch_correct(hipStream_t s, int P, LineArgs a, const float* b, float* outp, float* outm,

@@ -33,15 +33,15 @@ __device__ __forceinline__ void chunk_of(long long n, long long& lo, long long& 
 // workgroup's ends, the outer j neighbour) is issued before the first arithmetic, from
 // clamped (always valid) line indices, and missing neighbours are selected away after.
 // DIR: the PCG direction update is fused in: p = z + beta p_old is formed on the fly at
-// every stencil point (the same value the separate update computes), written to pnew, and
-// q = H p; otherwise p = pold.
+// every stencil point (the same value the separate update computes) and written to pnew;
+// otherwise p = pold. q itself is not stored: the PCG update forms it again from p (the
+// same function, the same values), which saves its round trip through HBM.
 template <int P, bool DIR>
 __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restrict__ z,
                                                 const float* __restrict__ pold,
                                                 float* __restrict__ pnew,
                                                 const float* __restrict__ hd,
-                                                const float* __restrict__ ho,
-                                                float* __restrict__ q, double* partial,
+                                                const float* __restrict__ ho, double* partial,
                                                 const DevState* st) {
   if (st->pcg_done) return;
   __shared__ float sp[EPI_LINE_WAVES][64 * P];   // p of the workgroup's lines, face order
@@ -57,7 +57,6 @@ __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restr
   const int NF = a.M + 1;
   const int jj = lc % a.m2, kk = lc / a.m2;
   const size_t base = (size_t)lc * NF;
-  const float av = a.alpha * a.v;
   const bool j0 = jj > 0, j1 = jj < a.m2 - 1, k0 = kk > 0, k1 = kk < a.m3 - 1;
   // the j neighbours from LDS when they belong to this workgroup's lines
   const bool jm_lds = j0 && wave > 0, jp_lds = j1 && wave < EPI_LINE_WAVES - 1;
@@ -92,38 +91,15 @@ __global__ __launch_bounds__(256) void k_matvec(LineArgs a, const float* __restr
     sp[wave][i] = pc[j];
   }
   __syncthreads();
-  const float* spm = jm_lds ? sp[wave - 1] : nullptr;
-  const float* spp = jp_lds ? sp[wave + 1] : nullptr;
+  float y[P];
+  hjgn_apply<P>(a, NF, lane, j0, j1, k0, k1, pc, hdv, hov, pk0, pk1, pjo,
+                jm_lds ? sp[wave - 1] : nullptr, jp_lds ? sp[wave + 1] : nullptr, y);
 #pragma unroll
   for (int j = 0; j < P; ++j) {
     const int i = lane + 64 * j;
-    // faces i - 1 and i + 1 (lane shifts; across a 64-face block from the end lane)
-    float pp = dpp_prev_lane(pc[j]), ho_p = dpp_prev_lane(hov[j]), pn = dpp_next_lane(pc[j]);
-    if (j > 0) {
-      const float e0 = read_lane(pc[j - 1], 63), e1 = read_lane(hov[j - 1], 63);
-      if (lane == 0) {
-        pp = e0;
-        ho_p = e1;
-      }
-    }
-    if (j < P - 1) {
-      const float e2 = read_lane(pc[j + 1], 0);
-      if (lane == 63) pn = e2;
-    }
-    const bool ok = lv && (j < P - 1 || i < NF);
-    float y = hdv[j] * pc[j];
-    if (i > 0) y = fmaf(ho_p, pp, y);
-    if (i < NF - 1) y = fmaf(hov[j], pn, y);
-    float l2 = 0.0f, l3 = 0.0f;
-    if (j0) l2 += pc[j] - (spm ? spm[i] : pjo[j]);
-    if (j1) l2 += pc[j] - (spp ? spp[i] : pjo[j]);
-    if (k0) l3 += pc[j] - pk0[j];
-    if (k1) l3 += pc[j] - pk1[j];
-    y = fmaf(av, l2 * a.inv_h2sq + l3 * a.inv_h3sq, y);
-    if (ok) {
+    if (lv && (j < P - 1 || i < NF)) {
       if (DIR) store_stream(&pnew[base + i], pc[j]);
-      store_stream(&q[base + i], y);
-      acc[0] += (double)pc[j] * y;
+      acc[0] += (double)pc[j] * y[j];
     }
   }
   block_partials<1>(acc, partial, blockIdx.x);
@@ -413,16 +389,16 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs f, DevState* st) {
 // Launchers
 // ------------------------------------------------------------------------------------
 void launch_matvec(hipStream_t s, int P, LineArgs a, const float* z, const float* pold,
-                   float* pnew, const float* hdiag, const float* hoff, float* q, double* partial,
+                   float* pnew, const float* hdiag, const float* hoff, double* partial,
                    const DevState* st) {
   const int nb = line_blocks(a);
   a.nblk = nb;
   if (z != nullptr) {
     EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_matvec<PP, true>), dim3(nb), dim3(256), 0, s, a, z,
-                                         pold, pnew, hdiag, hoff, q, partial, st));
+                                         pold, pnew, hdiag, hoff, partial, st));
   } else {
     EPI_DISPATCH_P(P, hipLaunchKernelGGL((k_matvec<PP, false>), dim3(nb), dim3(256), 0, s, a,
-                                         nullptr, pold, nullptr, hdiag, hoff, q, partial, st));
+                                         nullptr, pold, nullptr, hdiag, hoff, partial, st));
   }
 }
 void launch_dot(hipStream_t s, long long n, const float* x, const float* y, double* partial) {
