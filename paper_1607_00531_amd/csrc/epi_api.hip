@@ -90,6 +90,9 @@ struct epi_problem {
   // captured ADMM chunk
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
+  // GN-PCG: four PCG iterations per graph, the first four of a solve ([0]) and any later
+  // four ([1]), per line-local preconditioner (BLOCK, JACOBI, NONE)
+  hipGraphExec_t pcg_exec[2][3] = {};
   int g_chunk = 0, g_sqp = 0, g_lagr = 0;
   float *g_b = nullptr, *g_z = nullptr, *g_u = nullptr;
   bool g_zop = false;
@@ -336,6 +339,11 @@ static void free_graph(epi_problem* p) {
   p->gexec = nullptr;
   p->graph = nullptr;
   p->g_chunk = 0;
+  for (auto& row : p->pcg_exec)
+    for (auto& g : row) {
+      if (g) (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
 }
 
 EPI_API void epi_destroy(epi_problem* p) {
@@ -1103,6 +1111,33 @@ EPI_API epi_status epi_profile_admm(epi_problem* p, float* d_b, float* d_z, floa
 // ------------------------------------------------------------------------------------
 // GN-PCG (Section 4.1)
 // ------------------------------------------------------------------------------------
+// One PCG iteration (Section 4.1, the inner solve of eq. GNstep): matvec with the direction
+// update, step length, update of x and r with the preconditioner (SGS: unpreconditioned
+// update, then the two sweeps), next beta. f carries the finalisation's constants.
+static void pcg_iteration(epi_problem* p, int it, int precond, bool sgs, FinArgs f) {
+  const int lb = line_blocks(p->la);
+  const long long n = p->n;
+  float* pbuf[2] = {p->p, p->t1};
+  float* pcur = pbuf[it & 1];
+  if (it == 0)
+    launch_matvec(p->exec, p->P, p->la, nullptr, pcur, nullptr, p->hd, p->ho, p->partial, p->st);
+  else
+    launch_matvec(p->exec, p->P, p->la, p->zz, pbuf[(it - 1) & 1], pcur, p->hd, p->ho,
+                  p->partial, p->st);
+  f.kind = FIN_PCG_ALPHA;
+  f.nb1 = lb;
+  launch_finalize(p->exec, f, p->st);
+  launch_pcg_update(p->exec, p->P, p->la, sgs ? EPI_PRECOND_NONE : precond, p->hd, p->ho, p->x,
+                    p->r, p->zz, pcur, p->partial, p->st);
+  if (sgs) {
+    launch_sgs(p->exec, p->P, p->la, p->hd, p->ho, p->r, p->zz, p->st, 1);
+    launch_sgs_finish(p->exec, n, p->r, p->zz, nullptr, p->partial, 0, p->st);
+  }
+  f.kind = FIN_PCG_UPDATE;
+  f.nb1 = sgs ? flat_blocks(n) : lb;
+  launch_finalize(p->exec, f, p->st);
+}
+
 EPI_API epi_status epi_precond_apply(epi_problem* p, const float* d_b, int32_t precond,
                                      const float* d_r, float* d_z) {
   if (!p || !d_b || !d_r || !d_z) return fail(EPI_EINVAL, "null argument");
@@ -1203,30 +1238,35 @@ EPI_API epi_status epi_solve_gnpcg(epi_problem* p, float* d_b, const epi_gn_opts
     f.nb1 = sgs ? flat_blocks(n) : lb;
     launch_finalize(p->exec, f, p->st);
     // the direction p alternates between two buffers: from the second PCG iteration on, the
-    // matvec forms p = z + beta p_old itself and writes it to the other buffer
-    float* pbuf[2] = {p->p, p->t1};
-    for (int it = 0; it < opts->pcg_max; ++it) {
-      float* pcur = pbuf[it & 1];
-      if (it == 0)
-        launch_matvec(p->exec, p->P, p->la, nullptr, pcur, nullptr, p->hd, p->ho, p->partial,
-                      p->st);
-      else
-        launch_matvec(p->exec, p->P, p->la, p->zz, pbuf[(it - 1) & 1], pcur, p->hd, p->ho,
-                      p->partial, p->st);
-      f.kind = FIN_PCG_ALPHA;
-      f.nb1 = lb;
-      launch_finalize(p->exec, f, p->st);
-      launch_pcg_update(p->exec, p->P, p->la, sgs ? EPI_PRECOND_NONE : opts->precond, p->hd,
-                        p->ho, p->x, p->r, p->zz, pcur, p->partial, p->st);
-      if (sgs) {
-        launch_sgs(p->exec, p->P, p->la, p->hd, p->ho, p->r, p->zz, p->st, 1);
-        launch_sgs_finish(p->exec, n, p->r, p->zz, nullptr, p->partial, 0, p->st);
+    // matvec forms p = z + beta p_old itself and writes it to the other buffer. Four
+    // iterations at a time, then a host check of the PCG stop; with a line-local
+    // preconditioner every full group of four is one graph launch (the kernels of an
+    // iteration after the stop return at once).
+    for (int it = 0; it < opts->pcg_max;) {
+      const int cnt = std::min(4, opts->pcg_max - it);
+      if (!sgs && cnt == 4) {
+        hipGraphExec_t& ge = p->pcg_exec[it == 0 ? 0 : 1][opts->precond];
+        if (!ge) {
+          hipGraph_t gr = nullptr;
+          HIPCHK(hipStreamBeginCapture(p->exec, hipStreamCaptureModeThreadLocal));
+          for (int k = 0; k < 4; ++k) pcg_iteration(p, it + k, opts->precond, false, f);
+          hipError_t e = hipGetLastError();
+          const hipError_t e2 = hipStreamEndCapture(p->exec, &gr);
+          if (e == hipSuccess) e = e2;
+          if (e == hipSuccess) e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+          if (gr) (void)hipGraphDestroy(gr);
+          if (e != hipSuccess) {
+            ge = nullptr;
+            return fail(EPI_EHIP, "PCG graph: %s", hipGetErrorString(e));
+          }
+        }
+        HIPCHK(hipGraphLaunch(ge, p->exec));
+      } else {
+        for (int k = 0; k < cnt; ++k) pcg_iteration(p, it + k, opts->precond, sgs, f);
+        CHKLAUNCH();
       }
-      f.kind = FIN_PCG_UPDATE;
-      f.nb1 = sgs ? flat_blocks(n) : lb;
-      launch_finalize(p->exec, f, p->st);
-      CHKLAUNCH();
-      if ((it & 3) == 3 && it + 1 < opts->pcg_max) {
+      it += cnt;
+      if (it < opts->pcg_max) {
         HIPCHK(hipMemcpyAsync(h, p->st, sizeof(DevState), hipMemcpyDeviceToHost, p->exec));
         HIPCHK(hipStreamSynchronize(p->exec));
         if (h->pcg_done) break;
