@@ -82,7 +82,7 @@ struct epi_problem {
   DctTables tab;
   // per-slice j-axis operators for one fixed rho (split-bfloat16, inside the t2 allocation;
   // zop_rho 0: not built)
-  unsigned short* zop = nullptr;
+  void* zop = nullptr;   // per-slice j-axis operators in the precision's fragments
   double zop_rho = 0.0;
   bool use_zop = false;
   double* hist = nullptr;
@@ -203,46 +203,13 @@ static float bf16_to_f(uint16_t h) {
   return x;
 }
 
-// Pack A (m x m, row-major, A[row][k]) into MFMA operand fragments.
-// bf16 (16x16x32): fragment (rt, ks) lane l holds A[16 rt + l%16][32 ks + 8 (l/16) + e], e<8;
-//   hi block followed by the lo block (a = hi + lo).
-// fp32 (16x16x4): fragment (rt, ks) lane l holds A[16 rt + l%16][4 ks + l/16].
-static std::vector<uint16_t> pack_bf16(const std::vector<double>& A, int m, int& RT, int& KS) {
-  RT = (m + 15) / 16;
-  KS = (m + 31) / 32;
-  const size_t nfr = (size_t)RT * KS * 64 * 8;
-  std::vector<uint16_t> out(2 * nfr, 0);
-  for (int rt = 0; rt < RT; ++rt)
-    for (int ks = 0; ks < KS; ++ks)
-      for (int l = 0; l < 64; ++l)
-        for (int e = 0; e < 8; ++e) {
-          const int row = 16 * rt + (l & 15), k = 32 * ks + 8 * (l >> 4) + e;
-          const double val = (row < m && k < m) ? A[(size_t)row * m + k] : 0.0;
-          const uint16_t hi = bf16_rn((float)val);
-          const uint16_t lo = bf16_rn((float)(val - (double)bf16_to_f(hi)));
-          const size_t idx = (((size_t)rt * KS + ks) * 64 + l) * 8 + e;
-          out[idx] = hi;
-          out[nfr + idx] = lo;
-        }
-  return out;
-}
-static std::vector<float> pack_f32(const std::vector<double>& A, int m, int& RT, int& KS) {
-  RT = (m + 15) / 16;
-  KS = (m + 3) / 4;
-  std::vector<float> out((size_t)RT * KS * 64, 0.0f);
-  for (int rt = 0; rt < RT; ++rt)
-    for (int ks = 0; ks < KS; ++ks)
-      for (int l = 0; l < 64; ++l) {
-        const int row = 16 * rt + (l & 15), k = 4 * ks + (l >> 4);
-        out[((size_t)rt * KS + ks) * 64 + l] = (row < m && k < m) ? (float)A[(size_t)row * m + k] : 0.0f;
-      }
-  return out;
-}
-
 // Even/odd split of the DCT for the split-bfloat16 kernels (c = ceil(m/2), f = floor(m/2)):
 // the even half holds rows k = 2r (forward: C[2r][q], q < c; inverse: C[2q][n], n, q < c),
 // the odd half rows k = 2r + 1 (forward: C[2r+1][q]; inverse: C[2q+1][n]; n, r, q < f), in
 // row tiles [0, RTh) and [RTh, 2 RTh) with KS steps of 32 over the half's own contraction.
+// Fragment (rt, ks) of v_mfma_f32_16x16x32_bf16: lane l holds the half's
+// A[16 (rt % RTh) + l % 16][32 ks + 8 (l / 16) + e], e < 8; the hi block, then the lo block
+// (a = hi + lo).
 static std::vector<uint16_t> pack_bf16_split(const std::vector<double>& C, int m, bool inverse,
                                              int& RT, int& KS) {
   const int ce = (m + 1) / 2, fo = m / 2;
@@ -270,53 +237,59 @@ static std::vector<uint16_t> pack_bf16_split(const std::vector<double>& C, int m
   return out;
 }
 
-static epi_status upload_matrix(int precision, const std::vector<double>& A, int m, void** dst,
-                                int& RT, int& KS) {
-  if (precision == EPI_PREC_MIXED) {
-    auto v = pack_bf16(A, m, RT, KS);
-    HIPCHK(hipMalloc(dst, v.size() * sizeof(uint16_t)));
-    HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-  } else {
-    auto v = pack_f32(A, m, RT, KS);
-    HIPCHK(hipMalloc(dst, v.size() * sizeof(float)));
-    HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice));
-  }
-  return EPI_OK;
+// The same split for the float32 kernels: fragment (rt, ks) lane l holds the half's
+// A[16 (rt % RTh) + l % 16][4 ks + l / 16]; KS = 4 RTh steps of 4 (the half's contraction
+// padded to whole 16-row tiles).
+static std::vector<float> pack_f32_split(const std::vector<double>& C, int m, bool inverse,
+                                         int& RT, int& KS) {
+  const int ce = (m + 1) / 2, fo = m / 2;
+  const int RTh = (ce + 15) / 16;
+  RT = 2 * RTh;
+  KS = 4 * RTh;
+  std::vector<float> out((size_t)RT * KS * 64, 0.0f);
+  for (int rt = 0; rt < RT; ++rt)
+    for (int ks = 0; ks < KS; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        const int half = rt / RTh, row = 16 * (rt % RTh) + (l & 15), q = 4 * ks + (l >> 4);
+        const int cnt = half ? fo : ce;
+        double val = 0.0;
+        if (row < cnt && q < cnt)
+          val = inverse ? C[(size_t)(2 * q + half) * m + row] : C[(size_t)(2 * row + half) * m + q];
+        out[((size_t)rt * KS + ks) * 64 + l] = (float)val;
+      }
+  return out;
 }
 
 epi_status epi::build_dct_tables(int m2, int m3, double h2, double h3, int precision,
                                  DctTables* t) {
-  std::vector<double> C, Ct;
-  int RT, KS;
+  std::vector<double> C;
   for (int axis = 2; axis <= 3; ++axis) {
     const int m = axis == 2 ? m2 : m3;
     const double h = axis == 2 ? h2 : h3;
     dct_host(m, C);
-    Ct.assign((size_t)m * m, 0.0);
-    for (int a = 0; a < m; ++a)
-      for (int j = 0; j < m; ++j) Ct[(size_t)j * m + a] = C[(size_t)a * m + j];
-    epi_status s;
     void** fw = axis == 2 ? &t->A2f : &t->A3f;
     void** iv = axis == 2 ? &t->A2i : &t->A3i;
     int& RTa = axis == 2 ? t->RT2 : t->RT3;
     int& KSa = axis == 2 ? t->KS2 : t->KS3;
-    if (precision == EPI_PREC_MIXED) {
-      // even/odd split; spectral data in half order (even k first, then odd k)
-      for (int inv = 0; inv < 2; ++inv) {
+    // even/odd split in both precisions; spectral data in half order (even k first, then
+    // odd k)
+    for (int inv = 0; inv < 2; ++inv) {
+      void** dst = inv ? iv : fw;
+      if (precision == EPI_PREC_MIXED) {
         auto v = pack_bf16_split(C, m, inv == 1, RTa, KSa);
-        void** dst = inv ? iv : fw;
         HIPCHK(hipMalloc(dst, v.size() * sizeof(uint16_t)));
         HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+      } else {
+        auto v = pack_f32_split(C, m, inv == 1, RTa, KSa);
+        HIPCHK(hipMalloc(dst, v.size() * sizeof(float)));
+        HIPCHK(hipMemcpy(*dst, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice));
       }
-    } else {
-      if ((s = upload_matrix(precision, C, m, fw, RT, KS)) != EPI_OK) return s;
-      if ((s = upload_matrix(precision, Ct, m, iv, RTa, KSa)) != EPI_OK) return s;
     }
     std::vector<float> lam(m);
     const int ce = (m + 1) / 2;
     for (int j = 0; j < m; ++j) {
-      // eigenvalue of spectral row j (natural order, or half order with the split)
-      const int k = (precision == EPI_PREC_MIXED) ? (j < ce ? 2 * j : 2 * (j - ce) + 1) : j;
+      // eigenvalue of spectral row j in half order
+      const int k = j < ce ? 2 * j : 2 * (j - ce) + 1;
       lam[j] = (float)((2.0 - 2.0 * cos(M_PI * k / m)) / (h * h));
     }
     float** dl = axis == 2 ? &t->lam2 : &t->lam3;
@@ -482,15 +455,12 @@ static epi_status setup_impl(const epi_grid* grid, const float* Ip, const float*
   HIPCHK(hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming));
   const size_t nb = (size_t)p->n * sizeof(float);
-  // split-bfloat16 problems keep the per-slice operators of the j-axis pass behind t2
+  // the per-slice operators of the j-axis pass (fixed rho) sit behind t2
   const size_t nb_al = (nb + 255) & ~(size_t)255;
-  const int ce2 = (p->m2 + 1) / 2;
-  const size_t zb = (grid->precision == EPI_PREC_MIXED && ce2 <= 128)
-                        ? zop_bytes(p->m2, p->m3, 2 * ((ce2 + 15) / 16), (ce2 + 31) / 32)
-                        : 0;
+  const size_t zb = zop_bytes(grid->precision, p->m2, p->m3);
   float** bufs[] = {&p->w, &p->t1, &p->t2, &p->g, &p->hd, &p->ho, &p->x, &p->r, &p->zz, &p->p};
   for (float** b : bufs) HIPCHK(hipMalloc(b, b == &p->t2 ? nb_al + zb : nb));
-  if (zb) p->zop = reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(p->t2) + nb_al);
+  if (zb) p->zop = reinterpret_cast<char*>(p->t2) + nb_al;
   const int lb = line_blocks(a);
   p->hard_blocks = p->L < 128 ? p->L : 128;
   size_t cap = (size_t)lb * NQ_EVAL;
@@ -692,7 +662,8 @@ static GemmArgs gemm_axis2(const epi_problem* p, const float* in, float* out) {
     g.dir = 2;
     g.A1 = p->zop;
     g.A2 = nullptr;
-    g.a_bstride = 2LL * p->tab.RT2 * p->tab.KS2 * 64;
+    // per slice: hi and lo blocks of 16-byte fragments (bfloat16), or floats (float32)
+    g.a_bstride = (p->grid.precision == EPI_PREC_MIXED ? 2LL : 1LL) * p->tab.RT2 * p->tab.KS2 * 64;
   }
   return g;
 }
@@ -706,12 +677,12 @@ static void launch_axis2(const epi_problem* p, int prec, const GemmArgs& g) {
 // once per rho); with an adaptive rho, or in float32, the fused pass applies the three.
 static epi_status prepare_zop(epi_problem* p, double rho, bool fixed_rho) {
   p->use_zop = false;
-  if (!p->zop || !fixed_rho) return EPI_OK;   // zop: split-bfloat16 problems only
+  if (!p->zop || !fixed_rho) return EPI_OK;
   if (p->zop_rho == 0.0)   // padding entries of the fragments stay zero
-    HIPCHK(hipMemsetAsync(p->zop, 0, zop_bytes(p->m2, p->m3, p->tab.RT2, p->tab.KS2), p->exec));
+    HIPCHK(hipMemsetAsync(p->zop, 0, zop_bytes(p->grid.precision, p->m2, p->m3), p->exec));
   if (p->zop_rho != rho) {
-    if (launch_build_zop(p->exec, p->m2, p->m3, p->grid.h[1], p->grid.h[2], p->grid.alpha, rho,
-                         p->tab.RT2, p->tab.KS2, p->zop))
+    if (launch_build_zop(p->exec, p->grid.precision, p->m2, p->m3, p->grid.h[1], p->grid.h[2],
+                         p->grid.alpha, rho, p->tab.RT2, p->tab.KS2, p->zop))
       return fail(EPI_EINVAL, "transform length %d not supported", p->m2);
     CHKLAUNCH();
     p->zop_rho = rho;

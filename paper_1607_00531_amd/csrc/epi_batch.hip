@@ -109,9 +109,13 @@ __global__ __launch_bounds__(PREC == 1 ? 64 * EPI_DCT_NW : 256) void k_batch_dct
     else
       dct_bf16_body<FUSED, EPI, KSM, EPI_DCT_NW>(g, batch, c0, local,
                                                  reinterpret_cast<unsigned short*>(lds_raw));
-  } else
-    dct_f32_body<FUSED, EPI, KSM * 8, SLOTS>(g, batch, c0, local,
+  } else if (FUSED && g.dir == 2) {
+    dct_f32_body<false, EPI, KSM * 4, SLOTS>(g, batch, c0, local,
                                              reinterpret_cast<float*>(lds_raw));
+  } else {
+    dct_f32_body<FUSED, EPI, KSM * 4, SLOTS>(g, batch, c0, local,
+                                             reinterpret_cast<float*>(lds_raw));
+  }
 }
 
 // one workgroup per slot: float64 reduction of the last pass's sums and the stopping test
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(256) void k_batch_finalize(BatchDev* bd) {
 // ------------------------------------------------------------------------------------
 static size_t dct_class_lds(int prec, bool small) {
   GemmArgs g{};
-  g.KS = small ? (prec == 1 ? 2 : 32) : (prec == 1 ? 4 : 64);   // bf16: steps of one half
+  g.KS = small ? (prec == 1 ? 2 : 16) : (prec == 1 ? 4 : 32);   // steps of one half
   g.RT = small ? 8 : 16;
   return dct_lds_bytes(prec, g);
 }
@@ -225,8 +229,7 @@ struct SlotHost {
   double* hist = nullptr;
   int hist_len = 0;
   DctTables tab;
-  unsigned short* zop = nullptr;   // per-slice j-axis operators (split-bfloat16, fixed rho;
-                                   // inside the t2 allocation)
+  void* zop = nullptr;   // per-slice j-axis operators (fixed rho; inside the t2 allocation)
   int64_t footprint = 0;
   epi_admm_opts opts{};
 };
@@ -236,10 +239,18 @@ int64_t workspace_bytes(const epi_grid* g, int max_iter) {
   const long long n = (M + 1) * m2 * m3;
   const long long tiles = std::max<long long>(tiles_axis3((int)M, (int)m2), tiles_axis2((int)M, (int)m3));
   const long long part = std::max<long long>(tiles * NQ_ADMM_E, 4096);
-  const long long tables = 4 * (m2 * m2 + m3 * m3) * 4 + 4 * (m2 + m3);
-  // the split-bfloat16 per-slice operators of a fixed-rho volume (counted for every volume)
-  const long long ce = (m2 + 1) / 2;
-  const long long zop = (long long)zop_bytes((int)m2, (int)m3, 2 * (int)((ce + 15) / 16), (int)((ce + 31) / 32));
+  // the packed DCT matrices (forward and inverse per axis, the larger of the two
+  // precisions' fragment layouts) and the eigenvalues
+  const auto mat = [](long long m) {
+    const long long ce = (m + 1) / 2, RTh = (ce + 15) / 16;
+    const long long bf = 2 * (2 * RTh) * ((ce + 31) / 32) * 64 * 8 * 2;   // hi and lo blocks
+    const long long f32 = (2 * RTh) * (4 * RTh) * 64 * 4;
+    return bf > f32 ? bf : f32;
+  };
+  const long long tables = 2 * (mat(m2) + mat(m3)) + 4 * (m2 + m3);
+  // the per-slice operators of a fixed-rho volume (counted for every volume, at the size of
+  // the split-bfloat16 fragments, which is at least that of the float32 ones)
+  const long long zop = (long long)zop_bytes(EPI_PREC_MIXED, (int)m2, (int)m3);
   return 3 * n * 4 + part * 8 + (long long)EPI_HIST_ROWS * std::max(max_iter, 1) * 8 + tables + zop;
 }
 
@@ -282,7 +293,8 @@ static void use_zop(const SlotHost& s, GemmArgs& g) {
   g.dir = 2;
   g.A1 = s.zop;
   g.A2 = nullptr;
-  g.a_bstride = 2LL * s.tab.RT2 * s.tab.KS2 * 64;
+  // per slice: hi and lo blocks of 16-byte fragments (bfloat16), or floats (float32)
+  g.a_bstride = (s.grid.precision == EPI_PREC_MIXED ? 2LL : 1LL) * s.tab.RT2 * s.tab.KS2 * 64;
 }
 
 // Release a slot: its workspace goes to the cache (the least recently cached one is
@@ -307,10 +319,7 @@ static epi_status take_workspace(epi_batch* bt, SlotHost& s, const epi_grid* gri
                                  const epi_admm_opts* opts) {
   const size_t nb = (size_t)s.n * sizeof(float);
   const size_t nb_al = (nb + 255) & ~(size_t)255;
-  const int ce2 = (s.m2 + 1) / 2;
-  const size_t zb = (bt->precision == EPI_PREC_MIXED && opts->rho_mode == EPI_RHO_FIXED && ce2 <= 128)
-                        ? zop_bytes(s.m2, s.m3, 2 * ((ce2 + 15) / 16), (ce2 + 31) / 32)
-                        : 0;
+  const size_t zb = opts->rho_mode == EPI_RHO_FIXED ? zop_bytes(bt->precision, s.m2, s.m3) : 0;
   const long long tiles = std::max(tiles_axis3(s.M, s.m2), tiles_axis2(s.M, s.m3));
   const size_t part = (size_t)std::max<long long>(tiles * NQ_ADMM_E, 4096);
   const size_t hist = (size_t)EPI_HIST_ROWS * s.hist_len;
@@ -360,13 +369,13 @@ static epi_status take_workspace(epi_batch* bt, SlotHost& s, const epi_grid* gri
   s.tab = ws.tab;
   s.zop = nullptr;
   if (zb) {
-    s.zop = reinterpret_cast<unsigned short*>(reinterpret_cast<char*>(ws.t2) + ws.t2_data);
+    s.zop = reinterpret_cast<char*>(ws.t2) + ws.t2_data;
     if (ws.zop_m2 != s.m2 || ws.zop_m3 != s.m3 || ws.zop_h2 != h2 || ws.zop_h3 != h3 ||
         ws.zop_alpha != grid->alpha || ws.zop_rho != opts->rho) {
       ws.zop_m2 = 0;
       if (hipMemsetAsync(s.zop, 0, zb, bt->exec) != hipSuccess ||
-          launch_build_zop(bt->exec, s.m2, s.m3, h2, h3, grid->alpha, opts->rho, s.tab.RT2,
-                           s.tab.KS2, s.zop) != 0 ||
+          launch_build_zop(bt->exec, bt->precision, s.m2, s.m3, h2, h3, grid->alpha, opts->rho,
+                           s.tab.RT2, s.tab.KS2, s.zop) != 0 ||
           hipGetLastError() != hipSuccess)
         return fail(EPI_EHIP, "slot operator build");
       ws.zop_m2 = s.m2;

@@ -32,13 +32,13 @@ __global__ __launch_bounds__(64 * EPI_DCT_NW) void k_dct_bf16(GemmArgs g) {
   dct_bf16_body<FUSED, EPI, KSM, EPI_DCT_NW>(g, batch, c0, t, lds_bf);
 }
 
-template <bool FUSED, int EPI, int KSM, int SLOTS>
+template <bool FUSED, int EPI, int KSH, int SLOTS>
 __global__ __launch_bounds__(256) void k_dct_f32(GemmArgs g) {
   if (g.done != nullptr && *g.done) return;
   extern __shared__ __attribute__((aligned(16))) float lds_f[];
   int batch, c0;
   const int t = dct_tile(g, batch, c0);
-  dct_f32_body<FUSED, EPI, KSM, SLOTS>(g, batch, c0, t, lds_f);
+  dct_f32_body<FUSED, EPI, KSH, SLOTS>(g, batch, c0, t, lds_f);
 }
 
 template <bool FUSED, int EPI, int KSM, int SLOTS>
@@ -48,10 +48,11 @@ static void launch_dct_t(hipStream_t s, int prec, const GemmArgs& g) {
   if (prec == 1)
     hipLaunchKernelGGL((k_dct_bf16<FUSED, EPI, KSM, SLOTS>), grid, dim3(64 * EPI_DCT_NW), lds, s, g);
   else
-    hipLaunchKernelGGL((k_dct_f32<FUSED, EPI, KSM * 8, SLOTS>), grid, dim3(256), lds, s, g);
+    hipLaunchKernelGGL((k_dct_f32<FUSED, EPI, KSM * 4, SLOTS>), grid, dim3(256), lds, s, g);
 }
 
-// rows <= 128: 4 contraction steps of 32 and 2 row tiles per wave; rows <= 256: 8 and 4
+// rows <= 128: 4 contraction steps of 32 (bfloat16; 16 steps of 4 per half in float32)
+// and 2 row tiles per wave; rows <= 256: 8 (32) and 4
 template <bool FUSED>
 static void launch_dct(hipStream_t s, int prec, const GemmArgs& g) {
   const bool small = g.rows <= 128;
@@ -97,13 +98,18 @@ __device__ __forceinline__ size_t zop_index(int h, int row, int q, int RTh, int 
   const int rt = h * RTh + row / 16, ks = q / 32, l = (row & 15) + 16 * ((q & 31) >> 3);
   return (((size_t)rt * KS + ks) * 64 + l) * 8 + (q & 7);
 }
+// the same for the float32 fragments (steps of 4): lane (row & 15) + 16 (q & 3)
+__device__ __forceinline__ size_t zop_index_f32(int h, int row, int q, int RTh, int KS) {
+  const int rt = h * RTh + row / 16, ks = q / 4, l = (row & 15) + 16 * (q & 3);
+  return ((size_t)rt * KS + ks) * 64 + l;
+}
 
 // One workgroup per (slice, half). Each thread accumulates 4 x 4 blocks of M_h (rows
 // 4 bi.., columns 4 bj.., bi <= bj; M_h is symmetric, the mirror is written from the same
 // sums) over r, with C_h zero-padded to a multiple of 4 in LDS.
 __global__ __launch_bounds__(256) void k_build_zop(int m2, int m3, double h2, double h3,
                                                    double alpha, double rho, int RT, int KS,
-                                                   unsigned short* __restrict__ out) {
+                                                   int f32, void* __restrict__ out_raw) {
   extern __shared__ __attribute__((aligned(16))) double zop_lds[];
   double* sc = zop_lds;                                       // [ZOP_MAXC]
   float* Ch = reinterpret_cast<float*>(zop_lds + ZOP_MAXC);   // [cnt][cp]
@@ -124,7 +130,9 @@ __global__ __launch_bounds__(256) void k_build_zop(int m2, int m3, double h2, do
   }
   __syncthreads();
   const size_t nfr = (size_t)RT * KS * 64 * 8;
-  unsigned short* o = out + (size_t)kb * 2 * nfr;
+  unsigned short* o = reinterpret_cast<unsigned short*>(out_raw) + (size_t)kb * 2 * nfr;
+  const size_t nf32 = (size_t)RT * KS * 64;     // float32: one block of RT x KS fragments
+  float* of = reinterpret_cast<float*>(out_raw) + (size_t)kb * nf32;
   const int ntask = nb * (nb + 1) / 2;
   for (int t = threadIdx.x; t < ntask; t += blockDim.x) {
     // task t -> (bi, bj) with bi <= bj, row-major over the upper triangle
@@ -156,6 +164,11 @@ __global__ __launch_bounds__(256) void k_build_zop(int m2, int m3, double h2, do
       for (int b = 0; b < 4; ++b) {
         const int row = 4 * bi + a, q = 4 * bj + b;
         if (row >= cnt || q >= cnt) continue;
+        if (f32) {
+          of[zop_index_f32(h, row, q, RTh, KS)] = (float)acc[a][b];
+          if (row != q) of[zop_index_f32(h, q, row, RTh, KS)] = (float)acc[a][b];
+          continue;
+        }
         const unsigned short hi = bf16_rne((float)acc[a][b]);
         const unsigned short lo =
             bf16_rne((float)(acc[a][b] - (double)__uint_as_float((unsigned)hi << 16)));
@@ -171,17 +184,20 @@ __global__ __launch_bounds__(256) void k_build_zop(int m2, int m3, double h2, do
   }
 }
 
-size_t zop_bytes(int m2, int m3, int RT, int KS) {
-  return (size_t)m3 * 2 * RT * KS * 64 * 8 * sizeof(unsigned short);
+size_t zop_bytes(int prec, int m2, int m3) {
+  const int ce = (m2 + 1) / 2, RTh = (ce + 15) / 16;
+  if (ce > ZOP_MAXC) return 0;
+  if (prec == 1) return (size_t)m3 * 2 * (2 * RTh) * ((ce + 31) / 32) * 64 * 8 * sizeof(unsigned short);
+  return (size_t)m3 * (2 * RTh) * (4 * RTh) * 64 * sizeof(float);
 }
 
-int launch_build_zop(hipStream_t s, int m2, int m3, double h2, double h3, double alpha,
-                     double rho, int RT, int KS, unsigned short* out) {
+int launch_build_zop(hipStream_t s, int prec, int m2, int m3, double h2, double h3, double alpha,
+                     double rho, int RT, int KS, void* out) {
   if ((m2 + 1) / 2 > ZOP_MAXC) return 1;
   const int ce = (m2 + 1) / 2, cp = (ce + 3) & ~3;
   const size_t lds = ZOP_MAXC * sizeof(double) + (size_t)ce * cp * sizeof(float);
   hipLaunchKernelGGL(k_build_zop, dim3(m3, 2), dim3(256), lds, s, m2, m3, h2, h3, alpha, rho,
-                     RT, KS, out);
+                     RT, KS, prec == 1 ? 0 : 1, out);
   return 0;
 }
 
@@ -192,7 +208,7 @@ template <bool FUSED, int EPI, int KSM, int SLOTS>
 static bool set_lds(int big) {
   bool bad = hipSuccess != hipFuncSetAttribute((const void*)k_dct_bf16<FUSED, EPI, KSM, SLOTS>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  bad |= hipSuccess != hipFuncSetAttribute((const void*)k_dct_f32<FUSED, EPI, KSM * 8, SLOTS>,
+  bad |= hipSuccess != hipFuncSetAttribute((const void*)k_dct_f32<FUSED, EPI, KSM * 4, SLOTS>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, big);
   return bad;
 }

@@ -62,8 +62,8 @@ __host__ __device__ inline size_t dct_tile_bytes(int prec, const GemmArgs& g) {
     // hi and lo tiles, both halves of the even/odd split (KS steps of 32 each) + padding
     in_tile = (size_t)2 * DCT_NT * (2 * g.KS * 32 + EPI_DCT_KPAD) * sizeof(unsigned short);
   } else {
-    // the fused pass writes back all 16-row tiles, which may exceed the padded contraction
-    const int rows = g.KS * 4 > g.RT * 16 ? g.KS * 4 : g.RT * 16;
+    // both halves' contraction blocks (KS steps of 4 each); the output needs RT 16-row tiles
+    const int rows = 2 * g.KS * 4 > g.RT * 16 ? 2 * g.KS * 4 : g.RT * 16;
     in_tile = (size_t)rows * (DCT_NT + 4) * sizeof(float);
   }
   const size_t t = in_tile > out_tile ? in_tile : out_tile;
@@ -80,23 +80,6 @@ __device__ __forceinline__ int dct_tile(const GemmArgs& g, int& batch, int& c0) 
   batch = t / g.col_tiles;
   c0 = (t % g.col_tiles) * DCT_NT;
   return t;
-}
-
-// Accumulators -> LDS tile [row][col] (float32, row stride DCT_NT + 4); row tile
-// rt = wave + NW s.
-template <int SLOTS, int NW>
-__device__ __forceinline__ void acc_to_lds(float* T, const f4 (&acc)[SLOTS][4], int wave,
-                                           int lane, int nslot) {
-#pragma unroll
-  for (int s = 0; s < SLOTS; ++s) {
-    if (s < nslot) {
-      const int r0 = (wave + NW * s) * 16 + (lane >> 4) * 4;
-#pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) T[(r0 + r) * (DCT_NT + 4) + ct * 16 + (lane & 15)] = acc[s][ct][r];
-    }
-  }
 }
 
 // Output row -> value of the LDS tile [row][col]. OUT_PLAIN: the row itself. With the
@@ -441,11 +424,18 @@ __device__ __forceinline__ void dct_bf16_body(const GemmArgs& g, int batch, int 
 }
 
 // ------------------------------------------------------------------------------------
-// float32 variant (v_mfma_f32_16x16x4_f32), same structure; LDS tile [k][col]
+// float32 variant (v_mfma_f32_16x16x4_f32) with the same even/odd decomposition, spectral
+// half order and per-slice operator (dir 2) as the split-bfloat16 one; four wavefronts,
+// the first two on the even half, the others on the odd half. Packed matrices: row tiles
+// [0, RTh) even, [RTh, 2 RTh) odd, KS = 4 RTh steps of 4 over the half's contraction
+// (padded to whole 16-row tiles, so a half's spectral rows fit its contraction block).
+// LDS tile [k][col] (row stride DCT_NT + 4): the even block in rows [0, 4 KS), the odd
+// block after it; the output reuses it as [row][col].
 // ------------------------------------------------------------------------------------
 template <int SLOTS>
-__device__ __forceinline__ void gemm_f32(const float* __restrict__ A, int KS, int wave, int lane,
-                                         int nslot, const float* L, f4 (&acc)[SLOTS][4]) {
+__device__ __forceinline__ void gemm_f32_half(const float* __restrict__ A, int KS, int rt0,
+                                              int rstep, int lane, int nslot, const float* L,
+                                              f4 (&acc)[SLOTS][4]) {
   const int LD = DCT_NT + 4;
   for (int ks = 0; ks < KS; ++ks) {
     float bv[4];
@@ -454,7 +444,7 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ A, int KS, in
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (s < nslot) {
-        const float av = A[((size_t)(wave + 4 * s) * KS + ks) * 64 + lane];
+        const float av = A[((size_t)(rt0 + rstep * s) * KS + ks) * 64 + lane];
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct)
           acc[s][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ct], acc[s][ct], 0, 0, 0);
@@ -463,63 +453,95 @@ __device__ __forceinline__ void gemm_f32(const float* __restrict__ A, int KS, in
   }
 }
 
-template <bool FUSED, int EPI, int KSM, int SLOTS>
+// KSH: maximum steps of 4 of one half (half length <= 4 KSH); SLOTS: row tiles per
+// wavefront (RTh <= 2 SLOTS).
+template <bool FUSED, int EPI, int KSH, int SLOTS>
 __device__ __forceinline__ void dct_f32_body(const GemmArgs& g, int batch, int c0, int pslot,
                                              float* lds_f) {
-  const int LD = DCT_NT + 4;
-  const int KP = g.KS * 4;
+  constexpr int LD = DCT_NT + 4;
+  const int N = g.rows, ce = (N + 1) / 2, fo = N / 2;
+  const int KPh = g.KS * 4;                        // contraction rows of one half
+  const int RTh = g.RT / 2;
+  const bool fwd_in = FUSED || g.dir != 1;
   const size_t bofs = (size_t)batch * g.bstride;
-  const float* in = g.in + bofs;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float* in = g.in + bofs + c0;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   {
-    const int col = threadIdx.x & (DCT_NT - 1);
-    const bool cok = c0 + col < g.ncol;
-    float v[KSM];   // KSM = maximum contraction steps of 4 rows (rows <= 4 KSM)
+    // fill: thread (column lane, rows q = wave + 4 i of both halves); all loads first
+    const unsigned lane4 = (unsigned)lane * 4u;
+    const bool cok = c0 + lane < g.ncol;
+    float va[KSH], vb[KSH];
 #pragma unroll
-    for (int q = 0; q < KSM; ++q) {
-      const int k = threadIdx.x / DCT_NT + 4 * q;
-      v[q] = (cok && k < g.rows) ? in[(size_t)k * g.ld + c0 + col] : 0.0f;
+    for (int it = 0; it < KSH; ++it) {
+      const int q = wave + 4 * it;
+      // forward: x_q and x_{N-1-q}; inverse: spectral rows q (even) and c + q (odd)
+      const bool oka = cok && it < g.KS && q < ce;
+      const bool okb = cok && it < g.KS && q < fo;
+      const int rb = fwd_in ? N - 1 - q : ce + q;
+      va[it] = oka ? ld_at<float>(in + (size_t)q * g.ld, lane4) : 0.0f;
+      vb[it] = okb ? ld_at<float>(in + (size_t)(okb ? rb : 0) * g.ld, lane4) : 0.0f;
     }
 #pragma unroll
-    for (int q = 0; q < KSM; ++q) {
-      const int k = threadIdx.x / DCT_NT + 4 * q;
-      if (k < KP) lds_f[k * LD + col] = v[q];
+    for (int it = 0; it < KSH; ++it) {
+      const int q = wave + 4 * it;
+      if (it < g.KS) {
+        const float a = va[it], b = vb[it];
+        // forward: the pair sum / difference (b = 0 for q >= f, so s_mid = x_mid)
+        float ev = fwd_in ? a + b : a;
+        float od = fwd_in ? a - b : b;
+        if (fwd_in && q >= fo) od = 0.0f;
+        lds_f[q * LD + lane] = ev;
+        lds_f[(KPh + q) * LD + lane] = od;
+      }
     }
   }
   __syncthreads();
-  const int nslot = (g.RT - wave + 3) / 4;
+  const int half = wave >> 1, lw = wave & 1;
+  const int rt0 = half * RTh + lw;                 // row tiles rt0 + 2 s of this half
+  const int nslot = (RTh - lw + 1) / 2;
+  const float* Lh = lds_f + (size_t)half * KPh * LD;
   f4 acc[SLOTS][4];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) acc[s][ct] = f4{0.f, 0.f, 0.f, 0.f};
-  gemm_f32<SLOTS>(reinterpret_cast<const float*>(g.A1), g.KS, wave, lane, nslot, lds_f, acc);
+  const float* A1 = reinterpret_cast<const float*>(g.A1) + (size_t)batch * g.a_bstride;
+  gemm_f32_half<SLOTS>(A1, g.KS, rt0, 2, lane, nslot, Lh, acc);
   if (FUSED) {
+    // spectral scale rho / (rho + alpha (lambda_row + lambda_batch)) in half order, written
+    // over this half's input block (rows < 16 RTh = KPh), then the inverse from it
     const float rho = (float)g.st->rho;
     const float lb = (g.lam_batch != nullptr) ? g.lam_batch[batch] : 0.0f;
-    __syncthreads();
+    const int cnt = half ? fo : ce;
+    __syncthreads();   // all waves finished reading the input tile
+    float* Lw = lds_f + (size_t)half * KPh * LD;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
       if (s < nslot) {
-        const int r0 = (wave + 4 * s) * 16 + (lane >> 4) * 4;
+        const int r0 = (lw + 2 * s) * 16 + (lane >> 4) * 4;   // spectral row within the half
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = r0 + r;
-          const float sc = (row < g.rows) ? rho * rcp_f(rho + g.alpha * (g.lam_row[row] + lb)) : 0.0f;
+          const float sc = (row < cnt) ? rho * rcp_f(rho + g.alpha * (g.lam_row[half * ce + row] + lb)) : 0.0f;
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) lds_f[row * LD + ct * 16 + (lane & 15)] = acc[s][ct][r] * sc;
+          for (int ct = 0; ct < 4; ++ct) Lw[row * LD + ct * 16 + (lane & 15)] = acc[s][ct][r] * sc;
         }
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[s][ct] = f4{0.f, 0.f, 0.f, 0.f};
       }
     }
     __syncthreads();
-    gemm_f32<SLOTS>(reinterpret_cast<const float*>(g.A2), g.KS, wave, lane, nslot, lds_f, acc);
+    gemm_f32_half<SLOTS>(reinterpret_cast<const float*>(g.A2), g.KS, rt0, 2, lane, nslot, Lh,
+                         acc);
   }
+  __syncthreads();   // the LDS tile is reused for the output
+  acc_rows_to_lds<SLOTS>(lds_f, acc, rt0, 2, lane, nslot);
   __syncthreads();
-  acc_to_lds<SLOTS, 4>(lds_f, acc, wave, lane, nslot);
-  __syncthreads();
-  tile_epilogue<EPI, 4, OUT_PLAIN>(g, lds_f, bofs, c0, pslot, 0);
+  if (FUSED || g.dir != 0)
+    tile_epilogue<EPI, 4, OUT_EVEN_ODD>(g, lds_f, bofs, c0, pslot, RTh * 16);
+  else
+    tile_epilogue<EPI, 4, OUT_HALF_ORDER>(g, lds_f, bofs, c0, pslot, RTh * 16);
   __syncthreads();
 }
 

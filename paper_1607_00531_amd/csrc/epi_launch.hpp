@@ -115,10 +115,11 @@ void launch_dct_axis3(hipStream_t s, int prec, const GemmArgs& g);
 void launch_dct_axis2_fused(hipStream_t s, int prec, const GemmArgs& g);
 // j-axis pass through the per-slice operators (g.dir = 2, g.A1 = operators, g.a_bstride)
 void launch_dct_axis2_op(hipStream_t s, int prec, const GemmArgs& g);
-// bytes of the per-slice operators; builds them for one rho (nonzero: unsupported length)
-size_t zop_bytes(int m2, int m3, int RT, int KS);
-int launch_build_zop(hipStream_t s, int m2, int m3, double h2, double h3, double alpha,
-                     double rho, int RT, int KS, unsigned short* out);
+// bytes of the per-slice operators in the fragments of precision prec (0: unsupported
+// length); builds them for one rho (nonzero: unsupported length)
+size_t zop_bytes(int prec, int m2, int m3);
+int launch_build_zop(hipStream_t s, int prec, int m2, int m3, double h2, double h3, double alpha,
+                     double rho, int RT, int KS, void* out);
 int dct_set_lds_limits();
 
 }  // namespace epi

@@ -67,7 +67,14 @@ def test_batch_footprint_covers_one_slot(m, max_iter):
     g.alpha, g.beta, g.gamma, g.precision = 50.0, 10.0, 1e-3, 1
     M, m2, m3 = m
     n, N = (M + 1) * m2 * m3, M * m2 * m3
-    need = 4 * (2 * N + 3 * n) + 3 * 4 * n + 6 * 8 * max_iter + 2 * 2 * (m2 * m2 + m3 * m3)
+    def packed(m):
+        # forward + inverse split matrices: split-bfloat16 fragments (hi and lo, steps of
+        # 32 per half) or float32 fragments (4 RTh steps of 4 per half)
+        ce = (m + 1) // 2
+        rth = (ce + 15) // 16
+        return 2 * max(2 * (2 * rth) * ((ce + 31) // 32) * 64 * 8 * 2, (2 * rth) * (4 * rth) * 64 * 4)
+
+    need = 4 * (2 * N + 3 * n) + 3 * 4 * n + 6 * 8 * max_iter + packed(m2) + packed(m3)
     assert lib.epi_batch_footprint(ctypes.byref(g), max_iter) >= need
 
 
