@@ -95,10 +95,25 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
     __syncthreads();
   }
 
+  // the transverse terms first (the sum for S and the cross-line Laplacian of the
+  // gradient), so that the four neighbour lines are dead before the interpolation
+  double acc[NQ_EVAL] = {0, 0, 0, 0, 0, 0};
+  float lapx[P];
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int i = P * lane + j;
+    if (valid && i < NF) {
+      const float d2 = nb[1][j] - b[j];   // forward difference to j+1 (0 if absent)
+      const float d3 = nb[3][j] - b[j];   // forward difference to k+1 (0 if absent)
+      acc[2] += (double)d2 * d2 * a.inv_h2sq + (double)d3 * d3 * a.inv_h3sq;
+    }
+    lapx[j] = ((b[j] - nb[0][j]) + (b[j] - nb[1][j])) * a.inv_h2sq +
+              ((b[j] - nb[2][j]) + (b[j] - nb[3][j])) * a.inv_h3sq;
+  }
+
   Cells<P> C;
   eval_cells<P, false, MODEL>(a, b, sIp, sIm, lane, C);
 
-  double acc[NQ_EVAL] = {0, 0, 0, 0, 0, 0};
   float phid[P], phidd[P];
 #pragma unroll
   for (int j = 0; j < P; ++j) {
@@ -121,12 +136,6 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
         acc[4] += 1.0;
       }
     }
-    const int i = P * lane + j;
-    if (valid && i < NF) {
-      const float d2 = nb[1][j] - b[j];   // forward difference to j+1 (0 if absent)
-      const float d3 = nb[3][j] - b[j];   // forward difference to k+1 (0 if absent)
-      acc[2] += (double)d2 * d2 * a.inv_h2sq + (double)d3 * d3 * a.inv_h3sq;
-    }
   }
 
   if (MODE >= 1) {
@@ -143,8 +152,7 @@ __global__ __launch_bounds__(256) void k_eval(LineArgs a, const float* __restric
       const int i = P * lane + j;
       float gv = a.v * (C.Jl[j] * C.r[j] + rpJ[j]);
       float lap = (gprev[j] - C.g[j]) * a.inv_hp;
-      lap += ((b[j] - nb[0][j]) + (b[j] - nb[1][j])) * a.inv_h2sq;
-      lap += ((b[j] - nb[2][j]) + (b[j] - nb[3][j])) * a.inv_h3sq;
+      lap += lapx[j];
       gv += av * lap;
       if (with_pen) gv += a.beta * a.v * (phdprev[j] - phid[j]) * a.inv_hp;
       out[0][j] = (i < NF) ? gv : 0.0f;
