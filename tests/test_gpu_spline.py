@@ -227,3 +227,38 @@ def test_spline_model_rejected_where_it_has_no_coefficients():
         with pytest.raises(EpiError) as e:
             Problem(Ip, Im, v.h, 5.0, **bad)
         assert e.value.status == EPI_EINVAL
+
+
+def test_spline_at_the_benchmark_size():
+    """240 x 200 x 110 (the benchmark's workload) with the smoothed spline model: objective
+    and gradient at the true field and at zero, and one ADMM iteration from the oracle's
+    state after two, in the benchmark's mixed precision."""
+    from synth import config_volume
+    v = config_volume("3d_240x200x110", 0)
+    v.Ip = v.Ip.astype(np.float32).astype(np.float64)
+    v.Im = v.Im.astype(np.float32).astype(np.float64)
+    P = _oracle(v, 50.0, 0.5)
+    with _problem(v, 50.0, 0.5) as pr:
+        for bb in (v.b_true.reshape(P.L, -1), np.zeros((P.L, P.M + 1))):
+            g = T(np.zeros(pr.shape_faces))
+            t = pr.objective(T(bb.reshape(pr.shape_faces)), True, grad=g)
+            o = O.objective(P, bb, True)
+            for key in ("J", "D", "S", "P"):
+                assert abs(t[key] - o[key]) <= J_REL * abs(o["J"]), (key, t[key], o[key])
+            go = O.gradient(P, bb, True).reshape(-1)
+            err = np.abs(N(g).reshape(-1) - go).max()
+            assert err <= 2e-4 * np.abs(go).max() + 1e-5 * _grad_scale(P, bb), err
+        rho = 1e3
+        b0, z0, u0, _ = O.solve_admm(P, rho=rho, max_iter=2, eps_abs=0, eps_rel=0)
+        b0, z0, u0 = (P.lines(x) for x in (b0, z0, u0))
+        bn, _, _ = O.bstep(P, b0, z0, u0, rho)
+        zn = O.zstep(P, bn + u0, rho)
+        un = u0 + bn - zn
+        sh = pr.shape_faces
+        b, z, u = T(b0.reshape(sh)), T(z0.reshape(sh)), T(u0.reshape(sh))
+        rep = pr.solve_admm(b, z, u, rho=rho, max_iter=1, eps_abs=0.0, eps_rel=0.0)
+        assert rep["iters"] == 1
+        for gpu, cpu in ((b, bn), (z, zn), (u, un)):
+            err = np.abs(N(gpu).reshape(P.L, -1) - cpu).max() / P.hp
+            print(f"one spline ADMM step at 240x200x110: {err:.2e} voxel")
+            assert err <= FIELD_VOX, err
