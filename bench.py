@@ -556,37 +556,69 @@ def precond_leg(dev, gn_steps=3, applies=5):
     return out
 
 
+def quality_leg(probs, vols, k=4):
+    """The user-visible result on the first k headline volumes (Section 5's quality columns,
+    synthetic truth only): SSD distance and normalised cross-correlation of the corrected
+    pair before (b = 0) and after the ADMM solve, and the field's error against the
+    synthetic truth in voxels (RMS and max over the PE faces)."""
+    import torch
+    out = []
+    for pr, v in list(zip(probs, vols))[:k]:
+        st = [torch.zeros(pr.shape_faces, device="cuda") for _ in range(3)]
+        q0 = pr.corrected_images(st[0])
+        rep = pr.solve_admm(*st, rho=RHO, max_iter=MAX_ITER, eps_abs=0.0, eps_rel=TOL,
+                            check_every=CHECK_EVERY)
+        q1 = pr.corrected_images(st[0])
+        err = (st[0].double().cpu().numpy() - v.b_true) / v.h[0]
+        out.append({"seed": v.seed, "iters": rep["iters"],
+                    "D": [round(q0["D"], 6), round(q1["D"], 6)],
+                    "ncc": [round(q0["ncc"], 5), round(q1["ncc"], 5)],
+                    "field_error_vox": {"rms": round(float(np.sqrt(np.mean(err ** 2))), 4),
+                                        "max": round(float(np.abs(err).max()), 4)},
+                    "true_field_max_vox": round(float(np.abs(v.b_true).max() / v.h[0]), 3)})
+    log(f"quality leg: {json.dumps(out)}")
+    return {"workload": f"first {k} headline volumes, ADMM to rel. residual {TOL:g}; corrected "
+                        "pair at b = 0 and at the solution, field against the synthetic truth",
+            "volumes": out}
+
+
 def multilevel_leg(imgs, vols, steps, levels=3):
     """The coarse-to-fine strategy of Section 4.4 (restart from the average of the coarser
     level's b and z, the paper's third strategy) on the headline volumes: every level
     solved to the headline's relative residual, set-up of every level (handles, tables)
-    inside the timed region. Reported beside the single-level headline, which solves the
-    finest grid from zero."""
+    inside the timed region. Two penalty schedules: the headline's fixed rho = 1e3, and the
+    paper's adaptive one (residual balancing from rho = 1e6 with the floor 1e2, Section 4.3).
+    Reported beside the single-level headline, which solves the finest grid from zero."""
     import torch
     from paper_1607_00531_amd import solve_multilevel_admm
     m3, m2, M = imgs[0][0].shape
     b = torch.zeros((m3, m2, M + 1), device=imgs[0][0].device)
-    per, lat = [], []
-    for i in range(steps):
-        (Ip, Im), v = imgs[i % len(imgs)], vols[i % len(vols)]
-        b.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = solve_multilevel_admm(Ip, Im, v.h, ALPHA, b, levels=levels, beta=BETA,
-                                  restart="average", rho=RHO, max_iter=MAX_ITER, eps_abs=0.0,
-                                  eps_rel=TOL, check_every=CHECK_EVERY)
-        torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t0)
-        per.append(r)
-    fine = [r["iters"][-1] for r in per]
-    out = {"workload": f"coarse-to-fine ADMM, {levels} levels ({' -> '.join('x'.join(map(str, s)) for s in per[0]['sizes'])}), "
-                       f"restart from the average of b and z, every level to rel. residual {TOL:g}",
-           "volumes_per_s": round(len(lat) / sum(lat), 3),
-           "p50_ms": round(1e3 * percentile(lat, 50), 2), "p99_ms": round(1e3 * percentile(lat, 99), 2),
-           "iters_per_level": [r["iters"] for r in per],
-           "finest_converged": int(sum(r["converged"][-1] for r in per)),
-           "finest_at_iteration_cap": int(sum(1 for x in fine if x >= MAX_ITER))}
-    log(f"multilevel leg: {json.dumps(out)}")
+    out = {}
+    for name, rho0, mode in (("fixed_rho", RHO, "fixed"), ("adaptive_rho_from_1e6", 1e6, "adapt_floor")):
+        per, lat = [], []
+        for i in range(steps):
+            (Ip, Im), v = imgs[i % len(imgs)], vols[i % len(vols)]
+            b.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = solve_multilevel_admm(Ip, Im, v.h, ALPHA, b, levels=levels, beta=BETA,
+                                      restart="average", rho=rho0, rho_mode=mode,
+                                      max_iter=MAX_ITER, eps_abs=0.0, eps_rel=TOL,
+                                      check_every=CHECK_EVERY)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+            per.append(r)
+        fine = [r["iters"][-1] for r in per]
+        out["levels"] = " -> ".join("x".join(map(str, s)) for s in per[0]["sizes"])
+        out[name] = {"volumes_per_s": round(len(lat) / sum(lat), 3),
+                     "p50_ms": round(1e3 * percentile(lat, 50), 2),
+                     "p99_ms": round(1e3 * percentile(lat, 99), 2),
+                     "iters_per_level": [r["iters"] for r in per],
+                     "finest_converged": int(sum(r["converged"][-1] for r in per)),
+                     "finest_at_iteration_cap": int(sum(1 for x in fine if x >= MAX_ITER))}
+        log(f"multilevel leg {name}: {json.dumps(out[name])}")
+    out["workload"] = (f"coarse-to-fine ADMM, {levels} levels, restart from the average of b "
+                       f"and z, every level to rel. residual {TOL:g}")
     return out
 
 
@@ -654,6 +686,8 @@ def main():
     ap.add_argument("--no-served", action="store_true", help="skip the request-stream leg")
     ap.add_argument("--no-spline", action="store_true", help="skip the spline image model leg")
     ap.add_argument("--no-multilevel", action="store_true", help="skip the coarse-to-fine leg")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the corrected-image / field-error report")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the preconditioner comparison on the 128x128x64 volume")
     ap.add_argument("--serve-seconds", type=float, default=20.0)
@@ -824,6 +858,8 @@ def main():
         log("served leg")
         served = served_leg(dev, args.serve_seconds, args.serve_rate, args.serve_bases, MAX_ITER)
 
+    quality = quality_leg(probs, vols) if not args.no_quality else None
+
     multilevel = None
     if not args.no_multilevel:
         log("multilevel leg")
@@ -886,6 +922,7 @@ def main():
         "preconditioners": precond,
         "spline_image_model": spline,
         "multilevel": multilevel,
+        "quality": quality,
         "cpu_baseline": base,
         "error_vs_oracle": err,
     }
