@@ -103,27 +103,51 @@ def algorithmic_bytes(M, m2, m3, zop=True):
     }
 
 
-def counter_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE summary,
-    or None when the kernel sources changed since those counters were taken."""
+def _profile_blob(fname):
+    """The machine-readable block of a committed profile summary, or None when it is missing
+    or the kernel sources changed since its counters were taken."""
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "admm_gnpcg_240x200x110_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", fname)
     try:
         txt = open(path).read()
         blob = json.loads(re.search(r"```json\n(.*?)\n```", txt, re.S).group(1))
     except (OSError, AttributeError, ValueError):
         return None
     csrc = os.path.join(ROOT, "paper_1607_00531_amd", "csrc")
-    for fname, h in blob["sources_sha256_16"].items():
+    for src, h in blob["sources_sha256_16"].items():
         try:
-            cur = hashlib.sha256(open(os.path.join(csrc, fname), "rb").read()).hexdigest()[:16]
+            cur = hashlib.sha256(open(os.path.join(csrc, src), "rb").read()).hexdigest()[:16]
         except OSError:
             return None
         if cur != h:
             return None
-    rec = blob["per_launch"].get(kernel)
+    return blob
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE summary,
+    or None when the kernel sources changed since those counters were taken."""
+    blob = _profile_blob("admm_gnpcg_240x200x110_hbm_counters.md")
+    rec = blob["per_launch"].get(kernel) if blob else None
     return rec["traffic_bytes"] if rec else None
+
+
+def counter_valu(kernel, launch_us):
+    """VALU issue rate of `kernel`: wave64 VALU instructions per launch (SQ_INSTS_VALU, from
+    the committed SQ-counter summary) over the launch time measured here, against the VALU
+    issue peak; None when the sources changed since the counters were taken."""
+    blob = _profile_blob("admm_gnpcg_240x200x110_sq_counters.md")
+    rec = blob["per_launch"].get(kernel) if blob else None
+    if not rec or not launch_us:
+        return None
+    peak = blob["peak_valu_wave_instructions_per_s"] / 1e9
+    ach = rec["valu_wave_instructions"] / (launch_us * 1e-6) / 1e9
+    return {"wave_instructions_per_launch": rec["valu_wave_instructions"],
+            "per_wave": rec["valu_per_wave"], "achieved": round(ach, 1), "peak": peak,
+            "unit": "G wave64 VALU instructions/s", "frac": round(ach / peak, 4),
+            "peak_rule": blob["peak_rule"], "source": "SQ_INSTS_VALU, profiles/"
+            "admm_gnpcg_240x200x110_sq_counters.md"}
 
 
 def percentile(xs, q):
@@ -818,7 +842,9 @@ def main():
                     "bytes_rule": "8 B per cell + 36 B per face (44 B per face)",
                     "us_per_iteration": round(iter_s * 1e6, 2),
                     "frac": round(mbytes["iteration"] / iter_s / 1e9 / peak, 4),
-                    "timing": "timed region / ADMM iterations (set-up and host polls included)"}}
+                    "timing": "timed region / ADMM iterations (set-up and host polls included)"},
+                # what limits the kernel: vector-ALU issue, from the committed SQ counters
+                "valu": counter_valu(dom, t_dom)}
     iter_us = 1e3 * sum(k["total_ms"] for k in kernels.values()) / max(prof["iters"], 1)
     log(f"profile: {json.dumps(kernels)}")
 

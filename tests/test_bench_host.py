@@ -69,3 +69,16 @@ def test_counter_traffic_keys_on_the_kernel_sources():
     t = bench.counter_traffic("bstep")
     assert t is None or t > bench.algorithmic_bytes(240, 200, 110)["bstep"] * 0.9
     assert bench.counter_traffic("no_such_kernel") is None
+
+
+def test_counter_valu_keys_on_the_kernel_sources():
+    import bench
+    v = bench.counter_valu("bstep", 33.0)
+    if v is not None:
+        # one b-step launch: 22,000 wavefronts (one per PE line) of some hundreds of VALU
+        # instructions each; the issue peak is 1024 SIMDs x 2.4 GHz / 4 cycles
+        assert v["peak"] == 1024 * 2.4 / 4
+        assert 22000 * 100 < v["wave_instructions_per_launch"] < 22000 * 2000
+        assert abs(v["frac"] - v["achieved"] / v["peak"]) < 1e-3
+    assert bench.counter_valu("no_such_kernel", 33.0) is None
+    assert bench.counter_valu("bstep", 0.0) is None
